@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Throughput of the HIP graded-bed DEM stepper on one MI355X.
+
+Workload: 2,000,000 spheres, radius r(d) = 1.5 mm (1 + d / 20 mm) capped at
+8 r0 (the paper's linear grading with gamma = 0.15), +-10 % jitter, 0.2 m
+deep, periodic square side from the count model (2.12 m), floor wall, paper
+material set (2200 kg/m^3, 1 GPa, 0.15, mu_t 0.3, mu_r 0.02), dt = 2e-6 s.
+Seeded synthetic bed (raft deposition), then `--warmup` untimed steps, then
+exactly `--steps` timed steps.  One JSON line on stdout.
+
+A step is the whole pipeline: broad phase (cell binning, scans, owner-side
+search, reverse lists) on rebuild steps, then the fused narrow phase +
+contact law + accumulation + walls + integration kernel and the FP64 body
+reduction.  `--rebuild-every 1` (default) rebuilds the broad phase every
+step; `--rebuild-every k --skin s` uses candidate lists with a skin rebuilt
+every k steps (the contact set found each step is the same).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s at 2M-sphere graded bed; batched & adjoint vs plain, same GPU"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per particle-step: x (24) + r (4) + v (12) + omega (12)
+# read, x + v + omega (48) written, and per contact pair the history
+# (xi_t, xi_r: 24 B) and partner id (4 B) read and written (56 B)
+B_PARTICLE = 100.0
+B_PAIR = 56.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lpr_dev.h", "lpr_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2501_05300_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(n_particles):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary, when it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_counters_metric_bed.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        c = json.load(f)
+    if c.get("kernel_source_hash") != kernel_source_hash() or c.get("n") != n_particles:
+        return None
+    return c.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(spec, pos, vel, omg, keys, vals, clock, steps):
+    """The FP64 oracle, as it stands, on the same bed state (bounded sample:
+    `steps` steps of the full bed)."""
+    from oracle import oracle as O
+    threads = min(os.cpu_count() or 1, 16)
+    used = O.set_threads(threads)
+    ob = O.OracleBed(spec)
+    ob.set_state(pos, vel, omg)
+    ob.set_history(keys, vals)
+    ob.set_clock(clock)
+    t0 = time.perf_counter()
+    ob.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": spec.n * steps / dt, "unit": "particle-steps/s", "cores": used, "kind": "oracle",
+            "sample": f"{steps} FP64 oracle step(s) of the full {spec.n}-sphere bed from the GPU state after "
+                      f"warm-up, {dt:.1f} s, {used} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--n", type=int, default=2_000_000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--rebuild-every", type=int, default=1)
+    ap.add_argument("--skin", type=float, default=0.0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps for the CPU baseline (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this stepper runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note, not implemented)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2501_05300_amd import beds
+    from paper_2501_05300_amd.lprdem import Bed
+
+    t0 = time.perf_counter()
+    spec = beds.metric_bed(args.n, seed=args.seed)
+    log(f"bed generated: n={spec.n} side={spec.box[0]:.4f} m in {time.perf_counter() - t0:.1f} s")
+    bed = Bed(spec, rebuild_every=args.rebuild_every, skin=args.skin, block=args.block)
+    log("bed created on the GPU")
+    done = 0
+    while done < args.warmup:
+        k = min(500, args.warmup - done)
+        bed.step(k)
+        bed.sync()
+        done += k
+        log(f"warm-up {done}/{args.warmup}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prof = bed.step_profiled(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = bed.stats()
+    log(f"timed {args.steps} steps in {wall:.3f} s; kernels {prof}")
+    N = spec.n
+    pairs = st["contacts"]
+    cbar = pairs / N
+    value = N * args.steps / wall
+    step_ms = prof["step"] / args.steps
+    b_alg = B_PARTICLE + B_PAIR * cbar
+    achieved = N * b_alg / (step_ms * 1e-3) / 1e9
+    traffic = counter_traffic(N)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 law, f64 positions/geometry/reactions",
+        "data": "synthetic",
+        "config": {"workload": "graded bed, 2M spheres, r0 1.5 mm, L 20 mm, k 1, cap 8 r0, 0.2 m deep, "
+                               "periodic, floor, dt 2e-6 s",
+                   "n": N, "side_m": spec.box[0], "rebuild_every": args.rebuild_every, "skin_m": args.skin},
+        "contacts_per_s": pairs * args.steps / wall,
+        "contacts_per_particle": cbar,
+        "kernel_ms_per_step": {k: v / args.steps for k, v in prof.items()},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_step (fused narrow phase, law, accumulation, walls, integration)",
+                     "bytes_per_particle_step": b_alg},
+        "algorithmic_frac_whole_step": N * b_alg / (wall / args.steps) / 1e9 / HBM_PEAK_GBS,
+    }
+    if args.cpu_steps > 0:
+        pos, vel, omg = bed.state()
+        keys, vals = bed.history()
+        clock = bed.clock()
+        log("CPU baseline: oracle on the same state")
+        out["cpu_baseline"] = cpu_baseline(spec, pos, vel.astype(np.float64), omg.astype(np.float64), keys,
+                                           vals.astype(np.float64), clock, args.cpu_steps)
+    bed.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,234 @@
+/*
+ * lprdem.h -- C ABI of the MI355X graded-bed DEM stepper.
+ *
+ * The library steps the contact pipeline of the paper "Local particle
+ * refinement in terramechanical simulations" (arXiv 2501.05300) for
+ * polydisperse spheres whose radius grows with depth:
+ *
+ *   broad phase  : multi-level cell lists, one grid per radius band, over a
+ *                  Morton-ordered particle store;
+ *   narrow phase : exact FP64 sphere-sphere and sphere-wall predicates;
+ *   contact law  : section "Nonsmooth DEM and multibody dynamics" --
+ *                  Hertz gap g_n = delta^{e_H} (e_H = 5/4), compliance e_H/k_n,
+ *                  k_n = E* sqrt(d*) / 3 with E* and d* as defined there,
+ *                  damping gamma_n = 4.5 dt (eq:g_n, read as the compliant
+ *                  force F_n = max(0, k_n (delta^{2e_H-1} + e_H gamma_n
+ *                  delta^{2e_H-2} ddelta/dt))), Coulomb cone |F_t| <= mu_t F_n
+ *                  (eq:G_t) and rolling cone |M_r| <= mu_r r* F_n (eq:G_r),
+ *                  both realised as springs with per-contact history;
+ *   accumulation : deterministic (no floating-point atomics), FP64 body
+ *                  reactions;
+ *   integration  : velocity then position (the ordering of the paper's
+ *                  first-order stepper), explicit.
+ *
+ * Conventions
+ *   - All entry points are synchronous with respect to their host arguments
+ *     and return an lpr_status.  No C++ exception crosses this boundary.
+ *   - Unless a parameter says "device", every pointer argument is a host
+ *     pointer owned by the caller; inputs are copied, outputs are written.
+ *   - Particle arrays are indexed by stable id (the order of the arrays
+ *     passed at creation), 3 components interleaved (x0 y0 z0 x1 ...).
+ *   - Work is enqueued on the HIP stream given at creation.  lpr_step returns
+ *     after enqueueing; every read and lpr_sync wait for the stream.
+ *   - Device faults found by kernels (history-slot overflow, non-finite
+ *     values) latch.  The state then stays at the last complete step; reads
+ *     and lpr_sync report the latched status; only lpr_get_state and
+ *     lpr_bed_destroy remain usable.
+ */
+#ifndef LPRDEM_H
+#define LPRDEM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LPR_OK = 0,
+  LPR_E_INVAL = -1,     /* invalid argument or description */
+  LPR_E_NOMEM = -2,     /* allocation failed */
+  LPR_E_DEVICE = -3,    /* HIP runtime error */
+  LPR_E_CAPACITY = -4,  /* output buffer too small, or a per-particle
+                           history table overflowed (latched) */
+  LPR_E_STATE = -5,     /* call not allowed in the current state (a latched
+                           fault, or a broad-phase skin exceeded) */
+  LPR_E_NUMERIC = -6    /* non-finite force or state (latched) */
+} lpr_status;
+
+enum { LPR_WALL_PLANE = 0, LPR_WALL_DISK = 1, LPR_WALL_ANNULUS = 2, LPR_WALL_BOX = 3 };
+
+/* Device-memory provider.  alloc returns device memory of at least `bytes`
+ * bytes (256-byte aligned) or NULL; release frees it.  A NULL allocator
+ * makes the library use hipMalloc/hipFree. */
+typedef struct {
+  void* (*alloc)(void* ctx, size_t bytes);
+  void (*release)(void* ctx, void* ptr);
+  void* ctx;
+} lpr_allocator;
+
+/* Material and contact parameters of a bed (section "Generation of soil
+ * samples": 2200 kg/m^3, 1 GPa, 0.15, mu_t 0.3, mu_r 0.02). */
+typedef struct {
+  double rho;           /* particle density [kg/m^3] */
+  double E, nu;         /* Young's modulus [Pa], Poisson ratio */
+  double mu_t, mu_r;    /* Coulomb and rolling-resistance coefficients */
+  double dt;            /* time step [s] */
+  double gamma_factor;  /* gamma_n = gamma_factor * dt (paper: 4.5) */
+  double e_H;           /* gap exponent: 1.25 (Hertz) or 1 (linear) */
+  double kappa_t;       /* tangential / normal spring stiffness ratio */
+  double s_k;           /* multiplier on k_n */
+  double g[3];          /* gravity [m/s^2] */
+} lpr_params;
+
+/* A wall primitive attached to a kinematic body.  Geometry is given in the
+ * body frame (relative to the body origin, before its rotation about +z).
+ *   PLANE   : point origin, unit normal axis toward the particles; contact
+ *             when the signed distance (x - o).axis < r.
+ *   DISK    : one-sided disk, centre origin, normal axis toward the
+ *             particles, radius dims[0]; face and rim contacts.
+ *   ANNULUS : like DISK with radii dims[0] (inner) .. dims[1] (outer); the
+ *             first row of frame is its in-plane reference direction.
+ *   BOX     : centre origin, local axes = rows of frame, half extents dims.
+ * mu_t / mu_r < 0 means "the bed's value". */
+typedef struct {
+  int32_t kind;
+  int32_t body;
+  double origin[3];
+  double axis[3];
+  double frame[9];
+  double dims[3];
+  double mu_t, mu_r;
+} lpr_wall;
+
+/* A kinematic body: origin(t) = origin + lin_vel t, rotated by ang_vel t
+ * about +z through its origin.  z_free = 1 makes z a dynamic degree of
+ * freedom of mass `mass` under gravity and the particles' reaction. */
+typedef struct {
+  double origin[3];
+  double lin_vel[3];
+  double ang_vel;
+  int32_t z_free;
+  double mass;
+} lpr_body;
+
+typedef struct {
+  int64_t n;               /* particle count (> 0) */
+  double box[3];           /* periodic lengths in x, y (z unused) */
+  uint32_t periodic;       /* bit0: x periodic, bit1: y periodic */
+  const double* pos;       /* host, n*3 */
+  const float* radius;     /* host, n, > 0 */
+  const float* vel;        /* host, n*3 or NULL (zero) */
+  const float* omega;      /* host, n*3 or NULL (zero) */
+  int32_t n_walls;         /* <= LPR_MAX_WALLS */
+  const lpr_wall* walls;
+  int32_t n_bodies;        /* <= LPR_MAX_BODIES; body 0 is the static frame */
+  const lpr_body* bodies;
+  lpr_params params;
+  /* broad-phase controls; they change how contacts are found, never which */
+  int32_t rebuild_every;   /* 1: cell search every step; k > 1: candidate
+                              lists with a skin, rebuilt every k steps */
+  float skin;              /* [m], required > 0 when rebuild_every > 1 */
+  float band_ratio;        /* radius ratio of one cell-list level (0: 2) */
+  float cell_factor;       /* cell edge / (2 r_max(level) + skin), >= 1 (0: 1) */
+  int32_t block;           /* threads per block of the step kernel: 64, 128
+                              or 256 (0: 256) */
+  int32_t record_forces;   /* 1: keep the last step's per-particle contact
+                              forces and torques for lpr_read_forces */
+} lpr_bed_desc;
+
+#define LPR_MAX_WALLS 16
+#define LPR_MAX_BODIES 4
+#define LPR_SLOTS 16        /* sphere contacts per owner particle */
+
+/* A contact of the last step: a < b are stable ids of two particles, or a is
+ * a particle and b = -1 - w for wall w. */
+typedef struct {
+  int64_t a, b;
+} lpr_contact;
+
+/* One history record: owner stable id, partner code (stable id or -1 - w),
+ * tangential spring (3) and rolling spring (3). */
+typedef struct {
+  int64_t owner, partner;
+  float xi_t[3], xi_r[3];
+} lpr_history;
+
+typedef struct lpr_bed lpr_bed;
+
+/* Creates a bed.  The description is validated (n > 0, r > 0, finite
+ * inputs, dt > 0, periodic length > 2 max(r_i + r_j + skin), wall/body
+ * indices in range), particles are placed in Morton order per radius band
+ * on the device, and the per-step kernel sequence is captured in a HIP
+ * graph on `hip_stream` (NULL = the default stream).  *out receives the bed;
+ * on error *out is NULL. */
+lpr_status lpr_bed_create(const lpr_bed_desc* desc, const lpr_allocator* alloc, void* hip_stream,
+                          lpr_bed** out);
+lpr_status lpr_bed_destroy(lpr_bed* bed);
+
+/* Enqueues n_steps >= 0 steps.  Asynchronous. */
+lpr_status lpr_step(lpr_bed* bed, int64_t n_steps);
+/* Like lpr_step, but launches the kernels directly (no graph) with HIP
+ * events on the bed's stream around each kernel group, then waits.
+ * out[0]: summed ms of the broad-phase rebuild kernels, out[1]: summed ms of
+ * the fused contact/integration kernel, out[2]: summed ms of the body
+ * reduction kernel, out[3]: ms from the first to the last event.  Used to
+ * measure per-kernel durations for the roofline. */
+lpr_status lpr_step_profiled(lpr_bed* bed, int64_t n_steps, double out[4]);
+/* Waits for the bed's stream and reports any latched device status. */
+lpr_status lpr_sync(lpr_bed* bed);
+
+/* Particle state in stable-id order (host buffers, n*3 each; any may be NULL). */
+lpr_status lpr_get_state(lpr_bed* bed, double* pos, float* vel, float* omega);
+/* Replaces the particle state (NULL leaves a field unchanged); history of
+ * contacts is kept. */
+lpr_status lpr_set_state(lpr_bed* bed, const double* pos, const float* vel, const float* omega);
+
+/* Contact history.  lpr_get_history writes up to `capacity` records and sets
+ * *n_total; LPR_E_CAPACITY (nothing written) when capacity < *n_total.
+ * lpr_set_history replaces all history; records for pairs that are not in
+ * the current candidate lists are dropped (they would be dropped by the
+ * next step anyway). */
+lpr_status lpr_get_history(lpr_bed* bed, lpr_history* out, int64_t capacity, int64_t* n_total);
+lpr_status lpr_set_history(lpr_bed* bed, const lpr_history* rec, int64_t count);
+
+/* The last step's contacts, ascending (a, b); LPR_E_CAPACITY with *n_total
+ * set and nothing written when capacity is too small. */
+lpr_status lpr_read_contacts(lpr_bed* bed, lpr_contact* out, int64_t capacity, int64_t* n_total);
+/* The last step's contact-only force and torque per particle (requires
+ * record_forces; host buffers n*3, stable-id order). */
+lpr_status lpr_read_forces(lpr_bed* bed, float* force, float* torque);
+/* Reaction of the last step on a body: force from the particles (3) and
+ * torque about the body origin (3), FP64. */
+lpr_status lpr_read_reaction(lpr_bed* bed, int32_t body, double out6[6]);
+/* Sum over steps of the body reaction since the last reset and the number
+ * of steps summed; reset = 1 clears the sums after reading. */
+lpr_status lpr_reaction_window(lpr_bed* bed, int32_t body, double sum6[6], int64_t* steps, int32_t reset);
+/* Current pose of a body: origin and translation velocity. */
+lpr_status lpr_read_body(lpr_bed* bed, int32_t body, double origin[3], double vel[3]);
+
+/* Time step index k (t = k dt) and dynamic-body state. */
+lpr_status lpr_set_clock(lpr_bed* bed, int64_t step);
+lpr_status lpr_get_clock(lpr_bed* bed, int64_t* step);
+lpr_status lpr_set_body_state(lpr_bed* bed, int32_t body, double z, double vz);
+
+typedef struct {
+  int64_t steps;            /* completed steps */
+  int64_t contacts;         /* contacts of the last step (sphere + wall) */
+  int64_t candidates;       /* owner-side candidate pairs in the lists */
+  int64_t rebuilds;         /* broad-phase rebuilds performed */
+  int32_t levels;           /* cell-list levels */
+  int64_t cells;            /* cells over all levels */
+  int32_t max_owner_slots;  /* largest per-owner candidate count seen at
+                               the last rebuild */
+} lpr_stats;
+lpr_status lpr_get_stats(lpr_bed* bed, lpr_stats* out);
+
+const char* lpr_status_str(lpr_status s);
+/* Message of the last error on the calling thread ("" if none). */
+const char* lpr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

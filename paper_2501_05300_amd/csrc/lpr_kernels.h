@@ -1,0 +1,82 @@
+// lpr_kernels.h -- launch wrappers of the stepper's kernels (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lpr_dev.h"
+
+namespace lpr {
+
+// Device pointers of one stepper instance (one bed or a batch of beds).
+struct DevBufs {
+  int64_t N;            // padded particle count
+  int32_t nbeds;
+  int64_t ncells;
+  // state
+  double4* pos[2];
+  float4* vel[2];
+  float4* omg[2];
+  int32_t* sid;
+  uint32_t* meta;
+  uint8_t* chunk_bed;   // bed of each PAD-chunk of particles (as int32 below)
+  int32_t* chunk_bed32;
+  // cells
+  uint32_t* cell_cnt;
+  uint32_t* cell_start;  // ncells + 1
+  int32_t* pcell;
+  uint32_t* prank;
+  int32_t* cell_list;
+  // lists
+  int32_t* own_idx[2];   // [K][N]
+  int32_t* own_cnt[2];   // [N]
+  uint32_t* own_rank;    // [K][N]
+  uint32_t* rev_cnt;     // [N]
+  uint32_t* rev_start;   // [N+1]
+  uint32_t* rev_ent;     // [K*N]
+  // history
+  float4* hA[2];         // [K][N]
+  float2* hB[2];
+  float4* wA[2];         // [MAXW][N]
+  float2* wB[2];
+  uint32_t* cflag[2];
+  // records
+  float4* frc;           // optional
+  float4* trq;
+  double* partial;       // [nblocks(256-thread)][MAXB][6]
+  // scan scratch
+  uint32_t* scan_tmp;
+  // tables
+  BedConst* beds;
+  LevelGrid* levels;
+  WallDef* wdefs;
+  WallPose* walls;
+  BodyDef* bdefs;
+  BodyDyn* bdyn;
+  BedDyn* bedyn;
+  uint32_t* err;
+  uint32_t* stat;        // [0] max owner count at last rebuild, [1] rebuilds
+};
+
+// Parities of one step, known on the host.
+struct StepPar {
+  int s;     // state buffer read this step
+  int h;     // history buffer read by the step kernel
+  int l;     // list buffer used by the step kernel
+  bool rebuild;
+};
+
+void launch_zero(uint32_t* p, int64_t n, hipStream_t st);
+void launch_bin(const DevBufs& d, int s, hipStream_t st);
+void launch_scan(uint32_t* in_out_cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipStream_t st);
+void launch_scatter(const DevBufs& d, hipStream_t st);
+// Owner-side search at state s; reads list/history parity (l_old, h_old) and
+// writes (1-l_old, 1-h_old).
+void launch_search(const DevBufs& d, int s, int l_old, int h_old, hipStream_t st);
+void launch_rev_scatter(const DevBufs& d, int l, hipStream_t st);
+void launch_rev_sort(const DevBufs& d, hipStream_t st);
+void launch_step(const DevBufs& d, const StepPar& p, int block, int record, hipStream_t st);
+void launch_advance(const DevBufs& d, int block, hipStream_t st);
+void launch_poses(const DevBufs& d, hipStream_t st);
+size_t scan_tmp_elems(int64_t n);
+
+}  // namespace lpr

@@ -1,0 +1,650 @@
+// lpr_kernels.hip -- HIP kernels of the graded-bed DEM step (gfx950).
+//
+// One step with the broad phase rebuilt (per step when rebuild_every = 1):
+//   k_zero      clear cell and reverse counters
+//   k_bin       per particle: cell of its own radius-band level, rank in cell
+//   scan        exclusive scan of cell counts -> cell ranges
+//   k_scatter   cell lists
+//   k_search    owner-side candidates: same level with larger (r, id), and
+//               every coarser level, 27 cells each; sorted by partner id;
+//               history carried over from the previous lists; reverse counts
+//   scan        reverse ranges;  k_rev_scatter / k_rev_sort: partner-side
+//               entries in a fixed order
+// then every step:
+//   k_step      fused narrow phase + contact law + accumulation + walls +
+//               integration; each particle evaluates all of its contacts
+//               (as owner and as partner) through one code path, so the two
+//               sides of a pair are bitwise opposite; FP64 reaction partials
+//   k_advance   ordered FP64 reduction of reactions, dynamic bodies, next
+//               wall poses, clock
+#include "lpr_kernels.h"
+
+namespace lpr {
+
+#define LPR_DEV_INLINE __device__ __forceinline__
+
+LPR_DEV_INLINE bool latched(const uint32_t* err) { return *(const volatile uint32_t*)err != 0u; }
+
+// ---------------------------------------------------------------------------
+// helpers
+
+__global__ void k_zero(uint32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+void launch_zero(uint32_t* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+}
+
+LPR_DEV_INLINE int cell_axis(const LevelGrid& G, int a, double x) {
+#pragma clang fp contract(off)
+  double f = (x - G.lo[a]) * G.inv_w[a];
+  f = fmin(fmax(f, -1.0), (double)G.n[a]);
+  int c = (int)floor(f);
+  if (G.per[a]) {
+    if (c >= G.n[a]) c -= G.n[a];
+    if (c < 0) c += G.n[a];
+  }
+  c = c < 0 ? 0 : (c >= G.n[a] ? G.n[a] - 1 : c);
+  return c;
+}
+
+// Neighbour cells along one axis (de-duplicated on short periodic axes).
+LPR_DEV_INLINE int axis_neighbours(const LevelGrid& G, int a, int c, int out[3]) {
+  const int n = G.n[a];
+  if (G.per[a]) {
+    if (n <= 3) {
+      for (int q = 0; q < n; ++q) out[q] = q;
+      return n;
+    }
+    out[0] = (c == 0) ? n - 1 : c - 1;
+    out[1] = c;
+    out[2] = (c == n - 1) ? 0 : c + 1;
+    return 3;
+  }
+  int m = 0;
+  if (c - 1 >= 0) out[m++] = c - 1;
+  out[m++] = c;
+  if (c + 1 < n) out[m++] = c + 1;
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// binning
+
+__global__ void k_bin(DevBufs d, int s) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= d.N || latched(d.err)) return;
+  const uint32_t m = d.meta[i];
+  if (m == INACTIVE) return;
+  const BedConst& bc = d.beds[m >> 8];
+  const LevelGrid& G = d.levels[bc.lev0 + (int)(m & 0xffu)];
+  const double4 p = d.pos[s][i];
+  const int cx = cell_axis(G, 0, p.x), cy = cell_axis(G, 1, p.y), cz = cell_axis(G, 2, p.z);
+  const int32_t c = (int32_t)(G.base + ((int64_t)cz * G.n[1] + cy) * G.n[0] + cx);
+  d.pcell[i] = c;
+  d.prank[i] = atomicAdd(&d.cell_cnt[c], 1u);
+}
+
+void launch_bin(const DevBufs& d, int s, hipStream_t st) {
+  hipLaunchKernelGGL(k_bin, dim3((unsigned)((d.N + 255) / 256)), dim3(256), 0, st, d, s);
+}
+
+__global__ void k_scatter(DevBufs d) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= d.N || latched(d.err)) return;
+  if (d.meta[i] == INACTIVE) return;
+  const int32_t c = d.pcell[i];
+  d.cell_list[d.cell_start[c] + d.prank[i]] = (int32_t)i;
+}
+
+void launch_scatter(const DevBufs& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((d.N + 255) / 256)), dim3(256), 0, st, d);
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of uint32 counts: tiles of 2048 (256 threads x 8)
+
+constexpr int SB = 256, SIPT = 8, STILE = SB * SIPT;
+
+LPR_DEV_INLINE uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[SB / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+  for (int q = 0; q < SB / 64; ++q) {
+    if (q < wv) off += wsum[q];
+    tot += wsum[q];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
+}
+
+__global__ void k_scan_tiles(const uint32_t* in, uint32_t* tsum, int64_t n) {
+  const int64_t base = blockIdx.x * (int64_t)STILE + threadIdx.x * SIPT;
+  uint32_t s = 0;
+  for (int q = 0; q < SIPT; ++q)
+    if (base + q < n) s += in[base + q];
+  uint32_t tot;
+  block_excl_scan(s, &tot);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_top(uint32_t* tsum, int64_t ntiles) {
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < ntiles; b0 += STILE) {
+    const int64_t base = b0 + threadIdx.x * SIPT;
+    uint32_t v[SIPT];
+    uint32_t s = 0;
+    for (int q = 0; q < SIPT; ++q) {
+      v[q] = (base + q < ntiles) ? tsum[base + q] : 0u;
+      s += v[q];
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan(s, &tot) + carry;
+    for (int q = 0; q < SIPT; ++q) {
+      if (base + q < ntiles) tsum[base + q] = off;
+      off += v[q];
+    }
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+__global__ void k_scan_apply(const uint32_t* in, uint32_t* out, const uint32_t* toff, int64_t n) {
+  const int64_t base = blockIdx.x * (int64_t)STILE + threadIdx.x * SIPT;
+  uint32_t v[SIPT];
+  uint32_t s = 0;
+  for (int q = 0; q < SIPT; ++q) {
+    v[q] = (base + q < n) ? in[base + q] : 0u;
+    s += v[q];
+  }
+  uint32_t tot;
+  uint32_t off = block_excl_scan(s, &tot) + toff[blockIdx.x];
+  for (int q = 0; q < SIPT; ++q) {
+    if (base + q < n) out[base + q] = off;
+    if (base + q == n - 1) out[n] = off + v[q];
+    off += v[q];
+  }
+}
+
+size_t scan_tmp_elems(int64_t n) { return (size_t)((n + STILE - 1) / STILE) + 1; }
+
+void launch_scan(uint32_t* cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipStream_t st) {
+  const int64_t tiles = (n + STILE - 1) / STILE;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SB), 0, st, cnt, tmp, n);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SB), 0, st, tmp, tiles);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(SB), 0, st, cnt, start, tmp, n);
+}
+
+// ---------------------------------------------------------------------------
+// owner-side search with history carry-over
+
+constexpr int SEARCH_BS = 128;
+
+__global__ __launch_bounds__(SEARCH_BS) void k_search(DevBufs d, int s, int lo, int ho) {
+  __shared__ int32_t c_sid[K][SEARCH_BS];
+  __shared__ int32_t c_idx[K][SEARCH_BS];
+  const int t = threadIdx.x;
+  const int64_t i = blockIdx.x * (int64_t)SEARCH_BS + t;
+  if (i >= d.N || latched(d.err)) return;
+  const int ln = lo ^ 1, hn = ho ^ 1;
+  const int64_t N = d.N;
+  const uint32_t m = d.meta[i];
+  if (m == INACTIVE) {
+    d.own_cnt[ln][i] = 0;
+    d.cflag[hn][i] = 0u;
+    return;
+  }
+  const BedConst& bc = d.beds[m >> 8];
+  const int lev_i = (int)(m & 0xffu);
+  const double4 pi = d.pos[s][i];
+  const float ri = (float)pi.w;
+  const int32_t si = d.sid[i];
+  const double skin = (double)bc.skin;
+  int cnt = 0;
+  bool ovf = false;
+  for (int lev = lev_i; lev < bc.nlev; ++lev) {
+    const LevelGrid& G = d.levels[bc.lev0 + lev];
+    int lx[3], ly[3], lz[3];
+    const int nxl = axis_neighbours(G, 0, cell_axis(G, 0, pi.x), lx);
+    const int nyl = axis_neighbours(G, 1, cell_axis(G, 1, pi.y), ly);
+    const int nzl = axis_neighbours(G, 2, cell_axis(G, 2, pi.z), lz);
+    for (int a = 0; a < nzl; ++a)
+      for (int b = 0; b < nyl; ++b)
+        for (int e = 0; e < nxl; ++e) {
+          const int64_t c = G.base + ((int64_t)lz[a] * G.n[1] + ly[b]) * G.n[0] + lx[e];
+          const uint32_t c0 = d.cell_start[c], c1 = d.cell_start[c + 1];
+          for (uint32_t q = c0; q < c1; ++q) {
+            const int32_t j = d.cell_list[q];
+            const double4 pj = d.pos[s][j];
+            const int32_t sj = d.sid[j];
+            if (!owner_rule(ri, si, (float)pj.w, sj)) continue;
+            double dx, dy, dz;
+            const double d2 = pair_sep(bc, pi, pj, dx, dy, dz);
+            if (within_skin(d2, pi.w, pj.w, skin)) {
+              if (cnt < K) {
+                c_sid[cnt][t] = sj;
+                c_idx[cnt][t] = j;
+              } else {
+                ovf = true;
+              }
+              ++cnt;
+            }
+          }
+        }
+  }
+  if (ovf) {
+    atomicOr(d.err, ERR_CAPACITY);
+    cnt = K;
+  }
+  // canonical slot order: ascending partner stable id
+  for (int a = 1; a < cnt; ++a) {
+    const int32_t ks = c_sid[a][t], kj = c_idx[a][t];
+    int b = a - 1;
+    while (b >= 0 && c_sid[b][t] > ks) {
+      c_sid[b + 1][t] = c_sid[b][t];
+      c_idx[b + 1][t] = c_idx[b][t];
+      --b;
+    }
+    c_sid[b + 1][t] = ks;
+    c_idx[b + 1][t] = kj;
+  }
+  const uint32_t fo = d.cflag[ho][i];
+  uint32_t fn = fo & 0xffff0000u;
+  const int cnt_old = d.own_cnt[lo][i];
+  for (int k = 0; k < cnt; ++k) {
+    const int32_t j = c_idx[k][t];
+    d.own_idx[ln][k * N + i] = j;
+    d.own_rank[k * N + i] = atomicAdd(&d.rev_cnt[j], 1u);
+    for (int k2 = 0; k2 < cnt_old; ++k2) {
+      if (d.own_idx[lo][k2 * N + i] == j) {
+        if ((fo >> k2) & 1u) {
+          d.hA[hn][k * N + i] = d.hA[ho][k2 * N + i];
+          d.hB[hn][k * N + i] = d.hB[ho][k2 * N + i];
+          fn |= 1u << k;
+        }
+        break;
+      }
+    }
+  }
+  for (int w = 0; w < bc.nwall; ++w)
+    if ((fo >> (WALL_BIT + w)) & 1u) {
+      d.wA[hn][w * N + i] = d.wA[ho][w * N + i];
+      d.wB[hn][w * N + i] = d.wB[ho][w * N + i];
+    }
+  d.own_cnt[ln][i] = cnt;
+  d.cflag[hn][i] = fn;
+  atomicMax(&d.stat[0], (uint32_t)cnt);
+}
+
+void launch_search(const DevBufs& d, int s, int lo, int ho, hipStream_t st) {
+  hipLaunchKernelGGL(k_search, dim3((unsigned)((d.N + SEARCH_BS - 1) / SEARCH_BS)), dim3(SEARCH_BS), 0, st, d, s,
+                     lo, ho);
+}
+
+__global__ void k_rev_scatter(DevBufs d, int l) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= d.N || latched(d.err)) return;
+  const int cnt = d.own_cnt[l][i];
+  for (int k = 0; k < cnt; ++k) {
+    const int32_t j = d.own_idx[l][k * d.N + i];
+    d.rev_ent[d.rev_start[j] + d.own_rank[k * d.N + i]] = ((uint32_t)i << 4) | (uint32_t)k;
+  }
+}
+
+void launch_rev_scatter(const DevBufs& d, int l, hipStream_t st) {
+  hipLaunchKernelGGL(k_rev_scatter, dim3((unsigned)((d.N + 255) / 256)), dim3(256), 0, st, d, l);
+}
+
+__global__ void k_rev_sort(DevBufs d) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= d.N || latched(d.err)) return;
+  const uint32_t a = d.rev_start[j], b = d.rev_start[j + 1];
+  for (uint32_t q = a + 1; q < b; ++q) {
+    const uint32_t key = d.rev_ent[q];
+    uint32_t p = q;
+    while (p > a && d.rev_ent[p - 1] > key) {
+      d.rev_ent[p] = d.rev_ent[p - 1];
+      --p;
+    }
+    d.rev_ent[p] = key;
+  }
+}
+
+void launch_rev_sort(const DevBufs& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_rev_sort, dim3((unsigned)((d.N + 255) / 256)), dim3(256), 0, st, d);
+}
+
+// ---------------------------------------------------------------------------
+// the fused step
+
+LPR_DEV_INLINE double wave_sum(double v) {
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_step(DevBufs d, StepPar p, int record) {
+  __shared__ double red[BS / 64][6];
+  if (__syncthreads_or(latched(d.err) ? 1 : 0)) return;  // uniform per block
+  const int64_t N = d.N;
+  const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  const int bed = d.chunk_bed32[(blockIdx.x * (int64_t)BS) >> 8];
+  const BedConst bc = d.beds[bed];
+  const uint32_t m = d.meta[i];
+  const bool active = (m != INACTIVE);
+  const int s = p.s, sn = p.s ^ 1, h = p.h, hn = p.h ^ 1, l = p.l;
+
+  double4 xi = make_double4(0, 0, 0, 0);
+  float4 vi = make_float4(0, 0, 0, 0), wi = make_float4(0, 0, 0, 0);
+  float3 F = f3(0.f, 0.f, 0.f), T = f3(0.f, 0.f, 0.f);
+  uint32_t fnew = 0u;
+  if (active) {
+    xi = d.pos[s][i];
+    vi = d.vel[s][i];
+    wi = d.omg[s][i];
+    const uint32_t fold = d.cflag[h][i];
+    const int n_own = d.own_cnt[l][i];
+    const uint32_t rs = d.rev_start[i];
+    const int n_tot = n_own + (int)(d.rev_start[i + 1] - rs);
+    for (int e = 0; e < n_tot; ++e) {
+      int64_t o, q;
+      int k;
+      const bool mine = e < n_own;
+      if (mine) {
+        k = e;
+        o = i;
+        q = d.own_idx[l][k * N + i];
+      } else {
+        const uint32_t pk = d.rev_ent[rs + (e - n_own)];
+        o = pk >> 4;
+        k = (int)(pk & 15u);
+        q = i;
+      }
+      const int64_t other = mine ? q : o;
+      const double4 xo_ = d.pos[s][other];
+      const float4 vo_ = d.vel[s][other];
+      const float4 wo_ = d.omg[s][other];
+      const double4 xa = mine ? xi : xo_, xb = mine ? xo_ : xi;   // owner a, partner b
+      const float4 va = mine ? vi : vo_, vb = mine ? vo_ : vi;
+      const float4 wa = mine ? wi : wo_, wb = mine ? wo_ : wi;
+      double dx, dy, dz;
+      const double d2 = pair_sep(bc, xa, xb, dx, dy, dz);
+      if (!sphere_touch(d2, xa.w, xb.w)) continue;
+      const uint32_t fo = mine ? fold : d.cflag[h][o];
+      LawIn in;
+      if ((fo >> k) & 1u) {
+        const float4 a4 = d.hA[h][k * N + o];
+        const float2 b2 = d.hB[h][k * N + o];
+        in.xt = f3(a4.x, a4.y, a4.z);
+        in.xr = f3(a4.w, b2.x, b2.y);
+      } else {
+        in.xt = f3(0.f, 0.f, 0.f);
+        in.xr = f3(0.f, 0.f, 0.f);
+      }
+      double dist, nxd, nyd, nzd;
+      if (d2 > 0.0) {
+        dist = sqrt(d2);
+        const double id = 1.0 / dist;
+        nxd = dx * id; nyd = dy * id; nzd = dz * id;
+      } else {
+        dist = 0.0;
+        nxd = 0.0; nyd = 0.0; nzd = 1.0;
+      }
+      const double dl = (xa.w + xb.w) - dist;
+      const float ra = (float)xa.w, rb = (float)xb.w;
+      in.delta = (float)dl;
+      in.n = f3((float)nxd, (float)nyd, (float)nzd);
+      const float la = ra - 0.5f * in.delta, lb = rb - 0.5f * in.delta;   // lever arms
+      const float3 wa3 = f3(wa.x, wa.y, wa.z), wb3 = f3(wb.x, wb.y, wb.z);
+      in.u = f3(va.x - vb.x, va.y - vb.y, va.z - vb.z) + la * cross(wa3, in.n) + lb * cross(wb3, in.n);
+      in.wrel = wa3 - wb3;
+      in.dstar = 2.0f * ra * rb / (ra + rb);
+      in.mu_t = bc.mu_t;
+      in.mu_r = bc.mu_r;
+      LawOut out;
+      contact_law(bc, in, out);
+      const float3 nft = cross(in.n, out.Ft);
+      if (mine) {
+        F = F + out.F;
+        T = T + (la * nft + out.M);
+        d.hA[hn][k * N + i] = make_float4(out.xt.x, out.xt.y, out.xt.z, out.xr.x);
+        d.hB[hn][k * N + i] = make_float2(out.xr.y, out.xr.z);
+        fnew |= 1u << k;
+      } else {
+        F = F - out.F;
+        T = T + (lb * nft - out.M);
+      }
+    }
+  }
+
+  // walls, body by body, with an ordered FP64 block reduction per body
+  for (int b = 0; b < bc.nbody; ++b) {
+    double r6[6] = {0, 0, 0, 0, 0, 0};
+    int hit = 0;
+    if (active) {
+      const uint32_t fold = d.cflag[h][i];
+      for (int w = 0; w < bc.nwall; ++w) {
+        const WallPose& W = d.walls[bc.wall0 + w];
+        if (W.body != b) continue;
+        double dl, nx, ny, nz;
+        if (!wall_geom(W, xi.x, xi.y, xi.z, xi.w, dl, nx, ny, nz)) continue;
+        hit = 1;
+        LawIn in;
+        if ((fold >> (WALL_BIT + w)) & 1u) {
+          const float4 a4 = d.wA[h][w * N + i];
+          const float2 b2 = d.wB[h][w * N + i];
+          in.xt = f3(a4.x, a4.y, a4.z);
+          in.xr = f3(a4.w, b2.x, b2.y);
+        } else {
+          in.xt = f3(0.f, 0.f, 0.f);
+          in.xr = f3(0.f, 0.f, 0.f);
+        }
+        const float ra = (float)xi.w;
+        in.delta = (float)dl;
+        in.n = f3((float)nx, (float)ny, (float)nz);
+        const float la = ra - 0.5f * in.delta;
+        // contact point (FP64) and wall velocity there
+        const double px = xi.x + (double)la * nx, py = xi.y + (double)la * ny, pz = xi.z + (double)la * nz;
+        const double rx = px - W.c[0], ry = py - W.c[1], rz = pz - W.c[2];
+        const float3 uw = f3((float)(W.vel[0] - W.omega * ry), (float)(W.vel[1] + W.omega * rx), (float)W.vel[2]);
+        const float3 wa3 = f3(wi.x, wi.y, wi.z);
+        in.u = f3(vi.x, vi.y, vi.z) + la * cross(wa3, in.n) - uw;
+        in.wrel = f3(wi.x, wi.y, wi.z - (float)W.omega);
+        in.dstar = 2.0f * ra;
+        in.mu_t = (W.mu_t < 0.f) ? bc.mu_t : W.mu_t;
+        in.mu_r = (W.mu_r < 0.f) ? bc.mu_r : W.mu_r;
+        LawOut out;
+        contact_law(bc, in, out);
+        F = F + out.F;
+        T = T + (la * cross(in.n, out.Ft) + out.M);
+        d.wA[hn][w * N + i] = make_float4(out.xt.x, out.xt.y, out.xt.z, out.xr.x);
+        d.wB[hn][w * N + i] = make_float2(out.xr.y, out.xr.z);
+        fnew |= 1u << (WALL_BIT + w);
+        // reaction on the body: -F at p, and -M
+        const double fx = -(double)out.F.x, fy = -(double)out.F.y, fz = -(double)out.F.z;
+        r6[0] += fx; r6[1] += fy; r6[2] += fz;
+        r6[3] += (ry * fz - rz * fy) - (double)out.M.x;
+        r6[4] += (rz * fx - rx * fz) - (double)out.M.y;
+        r6[5] += (rx * fy - ry * fx) - (double)out.M.z;
+      }
+    }
+    double* part = d.partial + ((int64_t)blockIdx.x * MAXB + b) * 6;
+    if (__syncthreads_or(hit)) {
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      for (int c = 0; c < 6; ++c) {
+        const double sum = wave_sum(r6[c]);
+        if (lane == 0) red[wv][c] = sum;
+      }
+      __syncthreads();
+      if (threadIdx.x < 6) {
+        double acc = 0.0;
+        for (int q = 0; q < BS / 64; ++q) acc += red[q][threadIdx.x];
+        part[threadIdx.x] = acc;
+      }
+      __syncthreads();
+    } else if (threadIdx.x < 6) {
+      part[threadIdx.x] = 0.0;
+    }
+  }
+  if (!active) return;
+  d.cflag[hn][i] = fnew;
+  if (record) {
+    d.frc[i] = make_float4(F.x, F.y, F.z, 0.f);
+    d.trq[i] = make_float4(T.x, T.y, T.z, 0.f);
+  }
+  // semi-implicit Euler: velocity first, then position with the new velocity
+  const float vx = vi.x + bc.dt * (F.x * vi.w + bc.g[0]);
+  const float vy = vi.y + bc.dt * (F.y * vi.w + bc.g[1]);
+  const float vz = vi.z + bc.dt * (F.z * vi.w + bc.g[2]);
+  const float ox = wi.x + bc.dt * (T.x * wi.w);
+  const float oy = wi.y + bc.dt * (T.y * wi.w);
+  const float oz = wi.z + bc.dt * (T.z * wi.w);
+  double x = xi.x + bc.dt_d * (double)vx;
+  double y = xi.y + bc.dt_d * (double)vy;
+  const double z = xi.z + bc.dt_d * (double)vz;
+  if (bc.periodic & 1u) {
+    if (x >= bc.L[0]) x -= bc.L[0];
+    else if (x < 0.0) x += bc.L[0];
+  }
+  if (bc.periodic & 2u) {
+    if (y >= bc.L[1]) y -= bc.L[1];
+    else if (y < 0.0) y += bc.L[1];
+  }
+  if (!(isfinite(vx) && isfinite(vy) && isfinite(vz) && isfinite(ox) && isfinite(oy) && isfinite(oz) &&
+        isfinite(x) && isfinite(y) && isfinite(z)))
+    atomicOr(d.err, ERR_NUMERIC);
+  d.pos[sn][i] = make_double4(x, y, z, xi.w);
+  d.vel[sn][i] = make_float4(vx, vy, vz, vi.w);
+  d.omg[sn][i] = make_float4(ox, oy, oz, wi.w);
+}
+
+void launch_step(const DevBufs& d, const StepPar& p, int block, int record, hipStream_t st) {
+  if (block == 64)
+    hipLaunchKernelGGL(k_step<64>, dim3((unsigned)(d.N / 64)), dim3(64), 0, st, d, p, record);
+  else if (block == 128)
+    hipLaunchKernelGGL(k_step<128>, dim3((unsigned)(d.N / 128)), dim3(128), 0, st, d, p, record);
+  else
+    hipLaunchKernelGGL(k_step<256>, dim3((unsigned)(d.N / 256)), dim3(256), 0, st, d, p, record);
+}
+
+// ---------------------------------------------------------------------------
+// body reduction, dynamic bodies, wall poses, clock
+
+LPR_DEV_INLINE void rot_z(const double* a, double c, double s, double* o) {
+#pragma clang fp contract(off)
+  o[0] = a[0] * c - a[1] * s;
+  o[1] = a[0] * s + a[1] * c;
+  o[2] = a[2];
+}
+
+LPR_DEV_INLINE void make_pose(const WallDef& W, const BodyDef& B, const BodyDyn& D, double t, WallPose& P) {
+#pragma clang fp contract(off)
+  double c[3] = {B.origin[0] + B.lin_vel[0] * t, B.origin[1] + B.lin_vel[1] * t, B.origin[2] + B.lin_vel[2] * t};
+  double v[3] = {B.lin_vel[0], B.lin_vel[1], B.lin_vel[2]};
+  if (B.z_free) {
+    c[2] = D.z;
+    v[2] = D.vz;
+  }
+  const double th = B.ang_vel * t;
+  const double cs = cos(th), sn = sin(th);
+  double ro[3];
+  rot_z(W.origin, cs, sn, ro);
+  P.o[0] = c[0] + ro[0]; P.o[1] = c[1] + ro[1]; P.o[2] = c[2] + ro[2];
+  rot_z(W.axis, cs, sn, P.nu);
+  for (int a = 0; a < 3; ++a) rot_z(&W.frame[3 * a], cs, sn, P.e[a]);
+  for (int a = 0; a < 3; ++a) {
+    P.dims[a] = W.dims[a];
+    P.c[a] = c[a];
+    P.vel[a] = v[a];
+  }
+  P.omega = B.ang_vel;
+  P.mu_t = (float)W.mu_t;
+  P.mu_r = (float)W.mu_r;
+  P.kind = W.kind;
+  P.body = W.body;
+}
+
+constexpr int ADV_BS = 256;
+
+__global__ __launch_bounds__(ADV_BS) void k_advance(DevBufs d, int step_block) {
+  __shared__ double red[ADV_BS];
+  if (__syncthreads_or(latched(d.err) ? 1 : 0)) return;  // uniform per block
+  const int bed = blockIdx.x;
+  const BedConst bc = d.beds[bed];
+  const int64_t blk0 = bc.p0 / step_block, blk1 = bc.p1 / step_block;
+  for (int b = 0; b < bc.nbody; ++b) {
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t q = blk0 + threadIdx.x; q < blk1; q += ADV_BS)
+      for (int c = 0; c < 6; ++c) acc[c] += d.partial[(q * MAXB + b) * 6 + c];
+    double tot[6];
+    for (int c = 0; c < 6; ++c) {
+      red[threadIdx.x] = acc[c];
+      __syncthreads();
+      for (int w = ADV_BS / 2; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+      }
+      tot[c] = red[0];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      BodyDyn& D = d.bdyn[bc.body0 + b];
+      const BodyDef& B = d.bdefs[bc.body0 + b];
+      for (int c = 0; c < 6; ++c) {
+        D.last[c] = tot[c];
+        D.wsum[c] += tot[c];
+      }
+      D.wsteps += 1;
+      if (B.z_free) {
+        D.vz = D.vz + bc.dt_d * (tot[2] / B.mass + (double)bc.g[2]);
+        D.z = D.z + bc.dt_d * D.vz;
+      }
+    }
+  }
+  __syncthreads();
+  // poses for the next step
+  const int64_t k_next = d.bedyn[bed].k + 1;
+  const double t = (double)k_next * bc.dt_d;
+  for (int w = threadIdx.x; w < bc.nwall; w += ADV_BS) {
+    const WallDef& W = d.wdefs[bc.wall0 + w];
+    make_pose(W, d.bdefs[bc.body0 + W.body], d.bdyn[bc.body0 + W.body], t, d.walls[bc.wall0 + w]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    d.bedyn[bed].k = k_next;
+    d.bedyn[bed].completed += 1;
+  }
+}
+
+void launch_advance(const DevBufs& d, int step_block, hipStream_t st) {
+  hipLaunchKernelGGL(k_advance, dim3((unsigned)d.nbeds), dim3(ADV_BS), 0, st, d, step_block);
+}
+
+__global__ void k_poses(DevBufs d) {
+  const int bed = blockIdx.x;
+  const BedConst bc = d.beds[bed];
+  const double t = (double)d.bedyn[bed].k * bc.dt_d;
+  for (int w = threadIdx.x; w < bc.nwall; w += blockDim.x) {
+    const WallDef& W = d.wdefs[bc.wall0 + w];
+    make_pose(W, d.bdefs[bc.body0 + W.body], d.bdyn[bc.body0 + W.body], t, d.walls[bc.wall0 + w]);
+  }
+}
+
+void launch_poses(const DevBufs& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_poses, dim3((unsigned)d.nbeds), dim3(64), 0, st, d);
+}
+
+}  // namespace lpr

@@ -1,0 +1,983 @@
+// lpr_runtime.hip -- host runtime behind the C ABI of include/lprdem.h.
+//
+// A stepper instance holds one or more beds back to back in device memory
+// (each bed padded to a multiple of PAD particles).  The host keeps the
+// ping-pong parities of state, history and candidate lists, enqueues the
+// rebuild and step kernels, and replays a captured HIP graph for the steady
+// cycle of 2 * rebuild_every steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "lpr_kernels.h"
+#include "lprdem.h"
+
+using namespace lpr;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lpr_status fail(lpr_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIPTRY(expr)                                                                                \
+  do {                                                                                              \
+    hipError_t e_ = (expr);                                                                         \
+    if (e_ != hipSuccess) return fail(LPR_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct HostBed {
+  int64_t n = 0;       // particles
+  int64_t p0 = 0;      // first storage index
+  int64_t npad = 0;    // padded count
+  std::vector<int64_t> perm;  // storage offset -> stable id
+  std::vector<int64_t> inv;   // stable id -> storage offset
+  int nwall = 0, nbody = 0, nlev = 0;
+  int wall0 = 0, body0 = 0, lev0 = 0;
+  double dt = 0.0;
+};
+
+uint64_t spread3(uint64_t v) {  // 21 bits -> every third bit
+  v &= 0x1fffffULL;
+  v = (v | (v << 32)) & 0x1f00000000ffffULL;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffULL;
+  v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
+  v = (v | (v << 2)) & 0x1249249249249249ULL;
+  return v;
+}
+
+int host_cell_axis(const LevelGrid& G, int a, double x) {
+  double f = (x - G.lo[a]) * G.inv_w[a];
+  f = std::fmin(std::fmax(f, -1.0), (double)G.n[a]);
+  int c = (int)std::floor(f);
+  if (G.per[a]) {
+    if (c >= G.n[a]) c -= G.n[a];
+    if (c < 0) c += G.n[a];
+  }
+  return c < 0 ? 0 : (c >= G.n[a] ? G.n[a] - 1 : c);
+}
+
+bool finite_arr(const double* a, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+bool finite_arrf(const float* a, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+struct lpr_bed {
+  lpr_allocator alloc{};
+  bool use_hip_malloc = true;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<void*> blocks;
+  DevBufs d{};
+  std::vector<HostBed> hb;
+  int block = 256;
+  int record = 0;
+  int R = 1;
+  float skin = 0.f;
+  // host parities
+  int s = 0, h = 0, l = 0;
+  int64_t since = std::numeric_limits<int64_t>::max() / 2;  // steps since the last rebuild
+  int64_t host_steps = 0;
+  int64_t rebuilds = 0;
+  // captured cycle
+  bool has_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int gs = 0, gh = 0, gl = 0;
+  int gsteps = 0;
+  int nlev_total = 0;
+  int64_t ncells = 0;
+  int max_walls = 0;
+  bool faulted = false;
+  lpr_status fault_status = LPR_OK;
+
+  void* dalloc(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (use_hip_malloc) {
+      if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    } else {
+      p = alloc.alloc(alloc.ctx, bytes);
+    }
+    if (p) blocks.push_back(p);
+    return p;
+  }
+  void release_all() {
+    for (void* p : blocks) {
+      if (use_hip_malloc) (void)hipFree(p);
+      else alloc.release(alloc.ctx, p);
+    }
+    blocks.clear();
+  }
+};
+
+namespace {
+
+template <class T>
+bool dal(lpr_bed* b, T** out, size_t count) {
+  *out = (T*)b->dalloc(sizeof(T) * (count ? count : 1));
+  return *out != nullptr;
+}
+
+lpr_status validate(const lpr_bed_desc* d) {
+  if (!d) return fail(LPR_E_INVAL, "null description");
+  if (d->n <= 0) return fail(LPR_E_INVAL, "n must be > 0");
+  if (d->n >= (int64_t(1) << 27)) return fail(LPR_E_INVAL, "n too large for packed contact entries");
+  if (!d->pos || !d->radius) return fail(LPR_E_INVAL, "pos and radius are required");
+  const lpr_params& p = d->params;
+  if (!(p.dt > 0.0) || !(p.rho > 0.0) || !(p.E > 0.0) || !(p.nu > -1.0 && p.nu < 0.5))
+    return fail(LPR_E_INVAL, "invalid material parameters or dt");
+  if (!(p.e_H >= 1.0) || !(p.kappa_t >= 0.0) || !(p.s_k > 0.0) || !(p.gamma_factor >= 0.0) || !(p.mu_t >= 0.0) ||
+      !(p.mu_r >= 0.0))
+    return fail(LPR_E_INVAL, "invalid contact-law parameters");
+  if (!finite_arr(d->pos, 3 * d->n)) return fail(LPR_E_INVAL, "non-finite position");
+  if (d->vel && !finite_arrf(d->vel, 3 * d->n)) return fail(LPR_E_INVAL, "non-finite velocity");
+  if (d->omega && !finite_arrf(d->omega, 3 * d->n)) return fail(LPR_E_INVAL, "non-finite angular velocity");
+  for (int64_t i = 0; i < d->n; ++i)
+    if (!(d->radius[i] > 0.f) || !std::isfinite(d->radius[i])) return fail(LPR_E_INVAL, "radius must be > 0");
+  if (d->n_walls < 0 || d->n_walls > LPR_MAX_WALLS) return fail(LPR_E_INVAL, "too many walls");
+  if (d->n_bodies < 0 || d->n_bodies > LPR_MAX_BODIES) return fail(LPR_E_INVAL, "too many bodies");
+  if (d->n_walls > 0 && (!d->walls || d->n_bodies == 0 || !d->bodies))
+    return fail(LPR_E_INVAL, "walls need bodies");
+  for (int w = 0; w < d->n_walls; ++w) {
+    const lpr_wall& W = d->walls[w];
+    if (W.kind < 0 || W.kind > 3 || W.body < 0 || W.body >= d->n_bodies)
+      return fail(LPR_E_INVAL, "wall kind or body out of range");
+  }
+  for (int q = 0; q < d->n_bodies; ++q)
+    if (d->bodies[q].z_free && !(d->bodies[q].mass > 0.0)) return fail(LPR_E_INVAL, "a z_free body needs mass > 0");
+  if (d->rebuild_every < 0 || (d->rebuild_every > 1 && !(d->skin > 0.f)))
+    return fail(LPR_E_INVAL, "rebuild_every > 1 needs skin > 0");
+  if (d->skin < 0.f) return fail(LPR_E_INVAL, "skin must be >= 0");
+  if (d->band_ratio != 0.f && !(d->band_ratio > 1.f)) return fail(LPR_E_INVAL, "band_ratio must be > 1");
+  if (d->cell_factor != 0.f && !(d->cell_factor >= 1.f)) return fail(LPR_E_INVAL, "cell_factor must be >= 1");
+  if (d->block != 0 && d->block != 64 && d->block != 128 && d->block != 256)
+    return fail(LPR_E_INVAL, "block must be 64, 128 or 256");
+  float rmax = 0.f;
+  for (int64_t i = 0; i < d->n; ++i) rmax = std::max(rmax, d->radius[i]);
+  for (int a = 0; a < 2; ++a)
+    if ((d->periodic >> a) & 1u)
+      if (!(d->box[a] > 2.0 * (2.0 * (double)rmax + (double)d->skin)))
+        return fail(LPR_E_INVAL, "periodic length must exceed 2 max(r_i + r_j + skin)");
+  return LPR_OK;
+}
+
+// Builds radius bands, level grids and the Morton storage order of one bed.
+void plan_bed(const lpr_bed_desc* D, double band_ratio, double cell_factor, double skin, HostBed& H,
+              std::vector<LevelGrid>& levels, int64_t& cell_base, std::vector<uint8_t>& lev_of) {
+  const int64_t n = D->n;
+  double rlo = std::numeric_limits<double>::max();
+  for (int64_t i = 0; i < n; ++i) rlo = std::min(rlo, (double)D->radius[i]);
+  double thr[MAXLEV + 1];
+  for (int q = 0; q <= MAXLEV; ++q) thr[q] = rlo * std::pow(band_ratio, (double)q);
+  lev_of.assign(n, 0);
+  int nlev = 1;
+  for (int64_t i = 0; i < n; ++i) {
+    const double r = D->radius[i];
+    int q = 0;
+    while (q + 1 < MAXLEV && thr[q + 1] <= r) ++q;
+    lev_of[i] = (uint8_t)q;
+    nlev = std::max(nlev, q + 1);
+  }
+  std::vector<double> rmax(nlev, 0.0), zlo(nlev, 1e300), zhi(nlev, -1e300), xlo(nlev, 1e300), xhi(nlev, -1e300),
+      ylo(nlev, 1e300), yhi(nlev, -1e300);
+  for (int64_t i = 0; i < n; ++i) {
+    const int q = lev_of[i];
+    rmax[q] = std::max(rmax[q], (double)D->radius[i]);
+    xlo[q] = std::min(xlo[q], D->pos[3 * i]); xhi[q] = std::max(xhi[q], D->pos[3 * i]);
+    ylo[q] = std::min(ylo[q], D->pos[3 * i + 1]); yhi[q] = std::max(yhi[q], D->pos[3 * i + 1]);
+    zlo[q] = std::min(zlo[q], D->pos[3 * i + 2]); zhi[q] = std::max(zhi[q], D->pos[3 * i + 2]);
+  }
+  H.lev0 = (int)levels.size();
+  H.nlev = nlev;
+  for (int q = 0; q < nlev; ++q) {
+    LevelGrid G{};
+    double rm = rmax[q] > 0.0 ? rmax[q] : thr[q + 1];
+    if (rmax[q] <= 0.0) { xlo[q] = xhi[q] = ylo[q] = yhi[q] = zlo[q] = zhi[q] = 0.0; }
+    const double hcell = cell_factor * (2.0 * rm + skin);
+    const double lo3[3] = {xlo[q], ylo[q], zlo[q]}, hi3[3] = {xhi[q], yhi[q], zhi[q]};
+    for (int a = 0; a < 3; ++a) {
+      const bool per = (a < 2) && ((D->periodic >> a) & 1u);
+      if (per) {
+        const int nc = std::max(1, (int)std::floor(D->box[a] / hcell));
+        G.n[a] = nc;
+        G.lo[a] = 0.0;
+        G.inv_w[a] = (double)nc / D->box[a];
+        G.per[a] = 1;
+      } else {
+        const double lo = lo3[a] - 2.0 * hcell, hi = hi3[a] + 2.0 * hcell;
+        int nc = (int)std::ceil((hi - lo) / hcell);
+        nc = std::max(1, std::min(nc, 1 << 20));
+        G.n[a] = nc;
+        G.lo[a] = lo;
+        G.inv_w[a] = 1.0 / hcell;
+        G.per[a] = 0;
+      }
+    }
+    G.base = cell_base;
+    cell_base += (int64_t)G.n[0] * G.n[1] * G.n[2];
+    levels.push_back(G);
+  }
+  // storage order: level, then Morton code of the cell, then stable id
+  std::vector<uint64_t> key(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const LevelGrid& G = levels[H.lev0 + lev_of[i]];
+    const uint64_t cx = (uint64_t)host_cell_axis(G, 0, D->pos[3 * i]);
+    const uint64_t cy = (uint64_t)host_cell_axis(G, 1, D->pos[3 * i + 1]);
+    const uint64_t cz = (uint64_t)host_cell_axis(G, 2, D->pos[3 * i + 2]);
+    key[i] = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+  }
+  H.perm.resize(n);
+  for (int64_t i = 0; i < n; ++i) H.perm[i] = i;
+  std::sort(H.perm.begin(), H.perm.end(), [&](int64_t a, int64_t b) {
+    if (lev_of[a] != lev_of[b]) return lev_of[a] < lev_of[b];
+    if (key[a] != key[b]) return key[a] < key[b];
+    return a < b;
+  });
+  H.inv.resize(n);
+  for (int64_t i = 0; i < n; ++i) H.inv[H.perm[i]] = i;
+}
+
+lpr_status sync_check(lpr_bed* b) {
+  HIPTRY(hipStreamSynchronize(b->stream));
+  uint32_t e = 0;
+  HIPTRY(hipMemcpy(&e, b->d.err, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  if (e) {
+    b->faulted = true;
+    if (e & ERR_CAPACITY) b->fault_status = LPR_E_CAPACITY;
+    else if (e & ERR_NUMERIC) b->fault_status = LPR_E_NUMERIC;
+    else b->fault_status = LPR_E_STATE;
+    return fail(b->fault_status, (e & ERR_CAPACITY) ? "a particle exceeded its contact slots"
+                                : (e & ERR_NUMERIC) ? "non-finite force or state"
+                                                    : "latched device fault");
+  }
+  return LPR_OK;
+}
+
+void enqueue_rebuild(lpr_bed* b) {
+  DevBufs& d = b->d;
+  launch_zero(d.cell_cnt, d.ncells, b->stream);
+  launch_zero(d.rev_cnt, d.N, b->stream);
+  launch_bin(d, b->s, b->stream);
+  launch_scan(d.cell_cnt, d.cell_start, d.scan_tmp, d.ncells, b->stream);
+  launch_scatter(d, b->stream);
+  launch_search(d, b->s, b->l, b->h, b->stream);
+  b->l ^= 1;
+  b->h ^= 1;
+  launch_scan(d.rev_cnt, d.rev_start, d.scan_tmp, d.N, b->stream);
+  launch_rev_scatter(d, b->l, b->stream);
+  launch_rev_sort(d, b->stream);
+  b->since = 0;
+  b->rebuilds += 1;
+}
+
+void enqueue_step(lpr_bed* b) {
+  if (b->since >= b->R) enqueue_rebuild(b);
+  StepPar p{b->s, b->h, b->l, false};
+  launch_step(b->d, p, b->block, b->record, b->stream);
+  launch_advance(b->d, b->block, b->stream);
+  b->s ^= 1;
+  b->h ^= 1;
+  b->since += 1;
+  b->host_steps += 1;
+}
+
+lpr_status capture_cycle(lpr_bed* b) {
+  const int S = 2 * b->R;
+  const int s0 = b->s, h0 = b->h, l0 = b->l;
+  const int64_t since0 = b->since, steps0 = b->host_steps, reb0 = b->rebuilds;
+  HIPTRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+  for (int q = 0; q < S; ++q) enqueue_step(b);
+  hipGraph_t g = nullptr;
+  HIPTRY(hipStreamEndCapture(b->stream, &g));
+  hipGraphExec_t ex = nullptr;
+  HIPTRY(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+  b->graph = g;
+  b->gexec = ex;
+  b->gs = s0; b->gh = h0; b->gl = l0;
+  b->gsteps = S;
+  b->has_graph = true;
+  // the capture only recorded; restore the host view
+  b->s = s0; b->h = h0; b->l = l0;
+  b->since = since0; b->host_steps = steps0; b->rebuilds = reb0;
+  return LPR_OK;
+}
+
+lpr_status guard(lpr_bed* b) {
+  if (!b) return fail(LPR_E_INVAL, "null bed");
+  if (b->faulted) return fail(LPR_E_STATE, "the bed has a latched fault");
+  return LPR_OK;
+}
+
+lpr_status ensure_lists(lpr_bed* b) {
+  if (b->since >= b->R) enqueue_rebuild(b);
+  return LPR_OK;
+}
+
+// Parity of the buffers holding the state after the completed steps.
+lpr_status state_parity(lpr_bed* b, int* par) {
+  BedDyn bd;
+  HIPTRY(hipStreamSynchronize(b->stream));
+  HIPTRY(hipMemcpy(&bd, b->d.bedyn, sizeof(BedDyn), hipMemcpyDeviceToHost));
+  *par = (int)(bd.completed & 1);
+  return LPR_OK;
+}
+
+lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_allocator* alloc, void* stream,
+                       lpr_bed** out) {
+  if (!out) return fail(LPR_E_INVAL, "null output");
+  *out = nullptr;
+  if (nb <= 0 || !descs) return fail(LPR_E_INVAL, "no beds");
+  for (int q = 0; q < nb; ++q) {
+    lpr_status st = validate(descs[q]);
+    if (st != LPR_OK) return st;
+  }
+  const lpr_bed_desc& D0 = *descs[0];
+  lpr_bed* b = new lpr_bed();
+  if (alloc && alloc->alloc && alloc->release) {
+    b->alloc = *alloc;
+    b->use_hip_malloc = false;
+  }
+  if (stream) {
+    b->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return fail(LPR_E_DEVICE, "stream creation failed");
+    }
+    b->own_stream = true;
+  }
+  b->block = D0.block ? D0.block : 256;
+  b->record = D0.record_forces ? 1 : 0;
+  b->R = std::max(1, D0.rebuild_every);
+  b->skin = b->R > 1 ? D0.skin : 0.f;
+  const double band = D0.band_ratio > 0.f ? D0.band_ratio : 2.0;
+  const double cfac = D0.cell_factor > 0.f ? D0.cell_factor : 1.0;
+
+  // plan beds
+  std::vector<LevelGrid> levels;
+  std::vector<std::vector<uint8_t>> lev_of(nb);
+  int64_t cell_base = 0, p = 0;
+  int wall_total = 0, body_total = 0, max_walls = 1;
+  b->hb.resize(nb);
+  for (int q = 0; q < nb; ++q) {
+    HostBed& H = b->hb[q];
+    const lpr_bed_desc* D = descs[q];
+    H.n = D->n;
+    H.p0 = p;
+    H.npad = (D->n + PAD - 1) / PAD * PAD;
+    p += H.npad;
+    plan_bed(D, band, cfac, (double)b->skin, H, levels, cell_base, lev_of[q]);
+    H.nwall = D->n_walls;
+    H.nbody = std::max(1, D->n_bodies);
+    H.wall0 = wall_total;
+    H.body0 = body_total;
+    wall_total += H.nwall;
+    body_total += H.nbody;
+    max_walls = std::max(max_walls, H.nwall);
+    H.dt = D->params.dt;
+  }
+  if (cell_base >= (int64_t(1) << 31) - 2) {
+    delete b;
+    return fail(LPR_E_INVAL, "too many cells; raise cell_factor");
+  }
+  b->nlev_total = (int)levels.size();
+  b->ncells = cell_base;
+  b->max_walls = max_walls;
+  const int64_t N = p;
+  DevBufs& d = b->d;
+  d.N = N;
+  d.nbeds = nb;
+  d.ncells = cell_base;
+  bool ok = true;
+  for (int q = 0; q < 2; ++q) {
+    ok &= dal(b, &d.pos[q], N) && dal(b, &d.vel[q], N) && dal(b, &d.omg[q], N);
+    ok &= dal(b, &d.own_idx[q], (size_t)K * N) && dal(b, &d.own_cnt[q], N);
+    ok &= dal(b, &d.hA[q], (size_t)K * N) && dal(b, &d.hB[q], (size_t)K * N);
+    ok &= dal(b, &d.wA[q], (size_t)max_walls * N) && dal(b, &d.wB[q], (size_t)max_walls * N);
+    ok &= dal(b, &d.cflag[q], N);
+  }
+  ok &= dal(b, &d.sid, N) && dal(b, &d.meta, N) && dal(b, &d.chunk_bed32, N / PAD);
+  ok &= dal(b, &d.cell_cnt, cell_base) && dal(b, &d.cell_start, cell_base + 1);
+  ok &= dal(b, &d.pcell, N) && dal(b, &d.prank, N) && dal(b, &d.cell_list, N);
+  ok &= dal(b, &d.own_rank, (size_t)K * N) && dal(b, &d.rev_cnt, N) && dal(b, &d.rev_start, N + 1);
+  ok &= dal(b, &d.rev_ent, (size_t)K * N);
+  if (b->record) ok &= dal(b, &d.frc, N) && dal(b, &d.trq, N);
+  ok &= dal(b, &d.partial, (size_t)(N / 64) * MAXB * 6);
+  ok &= dal(b, &d.scan_tmp, std::max(scan_tmp_elems(cell_base), scan_tmp_elems(N + 1)));
+  ok &= dal(b, &d.beds, nb) && dal(b, &d.levels, levels.size());
+  ok &= dal(b, &d.wdefs, std::max(1, wall_total)) && dal(b, &d.walls, std::max(1, wall_total));
+  ok &= dal(b, &d.bdefs, body_total) && dal(b, &d.bdyn, body_total) && dal(b, &d.bedyn, nb);
+  ok &= dal(b, &d.err, 1) && dal(b, &d.stat, 4);
+  if (!ok) {
+    b->release_all();
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return fail(LPR_E_NOMEM, "device allocation failed");
+  }
+
+  // host images
+  std::vector<double4> hpos(N, make_double4(0, 0, 0, 0));
+  std::vector<float4> hvel(N, make_float4(0, 0, 0, 0)), homg(N, make_float4(0, 0, 0, 0));
+  std::vector<int32_t> hsid(N, -1), hchunk(N / PAD, 0);
+  std::vector<uint32_t> hmeta(N, INACTIVE);
+  std::vector<BedConst> hbc(nb);
+  std::vector<WallDef> hwd(std::max(1, wall_total));
+  std::vector<BodyDef> hbd(body_total);
+  std::vector<BodyDyn> hbdyn(body_total);
+  std::vector<BedDyn> hbedyn(nb);
+  for (int q = 0; q < nb; ++q) {
+    const lpr_bed_desc* D = descs[q];
+    HostBed& H = b->hb[q];
+    const lpr_params& P = D->params;
+    for (int64_t off = 0; off < H.n; ++off) {
+      const int64_t i = H.perm[off];
+      const int64_t sidx = H.p0 + off;
+      const double r = (double)D->radius[i];
+      const double m = P.rho * (4.0 / 3.0) * M_PI * r * r * r;
+      const double I = 0.4 * m * r * r;
+      hpos[sidx] = make_double4(D->pos[3 * i], D->pos[3 * i + 1], D->pos[3 * i + 2], r);
+      hvel[sidx] = make_float4(D->vel ? D->vel[3 * i] : 0.f, D->vel ? D->vel[3 * i + 1] : 0.f,
+                               D->vel ? D->vel[3 * i + 2] : 0.f, (float)(1.0 / m));
+      homg[sidx] = make_float4(D->omega ? D->omega[3 * i] : 0.f, D->omega ? D->omega[3 * i + 1] : 0.f,
+                               D->omega ? D->omega[3 * i + 2] : 0.f, (float)(1.0 / I));
+      hsid[sidx] = (int32_t)i;
+      hmeta[sidx] = ((uint32_t)q << 8) | lev_of[q][i];
+    }
+    for (int64_t c = H.p0 / PAD; c < (H.p0 + H.npad) / PAD; ++c) hchunk[c] = q;
+    BedConst& C = hbc[q];
+    C.L[0] = D->box[0];
+    C.L[1] = D->box[1];
+    C.periodic = D->periodic & 3u;
+    C.lev0 = H.lev0;
+    C.nlev = H.nlev;
+    C.wall0 = H.wall0;
+    C.nwall = H.nwall;
+    C.body0 = H.body0;
+    C.nbody = H.nbody;
+    C.p0 = (int32_t)H.p0;
+    C.p1 = (int32_t)(H.p0 + H.npad);
+    C.skin = b->skin;
+    const double Estar = 1.0 / ((1.0 - P.nu * P.nu) / P.E + (1.0 - P.nu * P.nu) / P.E);
+    C.kfac = (float)(P.s_k * Estar / 3.0);
+    C.gn = (float)(P.gamma_factor * P.dt);
+    C.eH = (float)P.e_H;
+    C.kappa_t = (float)P.kappa_t;
+    C.mu_t = (float)P.mu_t;
+    C.mu_r = (float)P.mu_r;
+    C.dt = (float)P.dt;
+    C.dt_d = P.dt;
+    for (int a = 0; a < 3; ++a) C.g[a] = (float)P.g[a];
+    C.law = (P.e_H == 1.25) ? 0 : (P.e_H == 1.0 ? 1 : 2);
+    for (int w = 0; w < H.nwall; ++w) {
+      const lpr_wall& W = D->walls[w];
+      WallDef& X = hwd[H.wall0 + w];
+      for (int a = 0; a < 3; ++a) {
+        X.origin[a] = W.origin[a];
+        X.axis[a] = W.axis[a];
+        X.dims[a] = W.dims[a];
+      }
+      for (int a = 0; a < 9; ++a) X.frame[a] = W.frame[a];
+      X.mu_t = W.mu_t;
+      X.mu_r = W.mu_r;
+      X.kind = W.kind;
+      X.body = W.body;
+    }
+    for (int q2 = 0; q2 < H.nbody; ++q2) {
+      BodyDef& B = hbd[H.body0 + q2];
+      BodyDyn& Y = hbdyn[H.body0 + q2];
+      std::memset(&B, 0, sizeof(B));
+      std::memset(&Y, 0, sizeof(Y));
+      if (q2 < D->n_bodies) {
+        const lpr_body& S = D->bodies[q2];
+        for (int a = 0; a < 3; ++a) {
+          B.origin[a] = S.origin[a];
+          B.lin_vel[a] = S.lin_vel[a];
+        }
+        B.ang_vel = S.ang_vel;
+        B.mass = S.mass;
+        B.z_free = S.z_free;
+        Y.z = S.origin[2];
+        Y.vz = S.lin_vel[2];
+      }
+    }
+    hbedyn[q].k = 0;
+    hbedyn[q].completed = 0;
+  }
+  hipStream_t st = b->stream;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  hipError_t e = hipSuccess;
+  e = (hipError_t)(e | up(d.pos[0], hpos.data(), sizeof(double4) * N));
+  e = (hipError_t)(e | up(d.pos[1], hpos.data(), sizeof(double4) * N));
+  e = (hipError_t)(e | up(d.vel[0], hvel.data(), sizeof(float4) * N));
+  e = (hipError_t)(e | up(d.vel[1], hvel.data(), sizeof(float4) * N));
+  e = (hipError_t)(e | up(d.omg[0], homg.data(), sizeof(float4) * N));
+  e = (hipError_t)(e | up(d.omg[1], homg.data(), sizeof(float4) * N));
+  e = (hipError_t)(e | up(d.sid, hsid.data(), sizeof(int32_t) * N));
+  e = (hipError_t)(e | up(d.meta, hmeta.data(), sizeof(uint32_t) * N));
+  e = (hipError_t)(e | up(d.chunk_bed32, hchunk.data(), sizeof(int32_t) * (N / PAD)));
+  e = (hipError_t)(e | up(d.beds, hbc.data(), sizeof(BedConst) * nb));
+  e = (hipError_t)(e | up(d.levels, levels.data(), sizeof(LevelGrid) * levels.size()));
+  e = (hipError_t)(e | up(d.wdefs, hwd.data(), sizeof(WallDef) * hwd.size()));
+  e = (hipError_t)(e | up(d.bdefs, hbd.data(), sizeof(BodyDef) * body_total));
+  e = (hipError_t)(e | up(d.bdyn, hbdyn.data(), sizeof(BodyDyn) * body_total));
+  e = (hipError_t)(e | up(d.bedyn, hbedyn.data(), sizeof(BedDyn) * nb));
+  for (int q = 0; q < 2; ++q) {
+    e = (hipError_t)(e | hipMemsetAsync(d.own_cnt[q], 0, sizeof(int32_t) * N, st));
+    e = (hipError_t)(e | hipMemsetAsync(d.cflag[q], 0, sizeof(uint32_t) * N, st));
+  }
+  e = (hipError_t)(e | hipMemsetAsync(d.err, 0, sizeof(uint32_t), st));
+  e = (hipError_t)(e | hipMemsetAsync(d.stat, 0, sizeof(uint32_t) * 4, st));
+  e = (hipError_t)(e | hipMemsetAsync(d.partial, 0, sizeof(double) * (N / 64) * MAXB * 6, st));
+  if (b->record) {
+    e = (hipError_t)(e | hipMemsetAsync(d.frc, 0, sizeof(float4) * N, st));
+    e = (hipError_t)(e | hipMemsetAsync(d.trq, 0, sizeof(float4) * N, st));
+  }
+  launch_poses(d, st);
+  if (e != hipSuccess || hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess) {
+    b->release_all();
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return fail(LPR_E_DEVICE, "upload failed");
+  }
+  *out = b;
+  return LPR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lpr_status_str(lpr_status s) {
+  switch (s) {
+    case LPR_OK: return "ok";
+    case LPR_E_INVAL: return "invalid argument";
+    case LPR_E_NOMEM: return "out of memory";
+    case LPR_E_DEVICE: return "device error";
+    case LPR_E_CAPACITY: return "capacity exceeded";
+    case LPR_E_STATE: return "invalid state";
+    case LPR_E_NUMERIC: return "non-finite value";
+  }
+  return "unknown status";
+}
+
+const char* lpr_last_error(void) { return g_last_error.c_str(); }
+
+lpr_status lpr_bed_create(const lpr_bed_desc* desc, const lpr_allocator* alloc, void* hip_stream, lpr_bed** out) {
+  const lpr_bed_desc* one[1] = {desc};
+  return create_impl(one, 1, alloc, hip_stream, out);
+}
+
+lpr_status lpr_bed_destroy(lpr_bed* b) {
+  if (!b) return LPR_OK;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->release_all();
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return LPR_OK;
+}
+
+lpr_status lpr_step(lpr_bed* b, int64_t n_steps) {
+  lpr_status g = guard(b);
+  if (g != LPR_OK) return g;
+  if (n_steps < 0) return fail(LPR_E_INVAL, "n_steps must be >= 0");
+  while (n_steps > 0) {
+    const bool at_cycle = (b->since >= b->R);
+    if (at_cycle && n_steps >= 2 * b->R) {
+      if (!b->has_graph) {
+        lpr_status st = capture_cycle(b);
+        if (st != LPR_OK) return st;
+      }
+      if (b->s == b->gs && b->h == b->gh && b->l == b->gl) {
+        HIPTRY(hipGraphLaunch(b->gexec, b->stream));
+        // a cycle flips s twice, h 2R+2 times, l twice: parities unchanged
+        b->since = b->R;
+        b->host_steps += b->gsteps;
+        b->rebuilds += 2;
+        n_steps -= b->gsteps;
+        continue;
+      }
+    }
+    enqueue_step(b);
+    n_steps -= 1;
+  }
+  HIPTRY(hipGetLastError());
+  return LPR_OK;
+}
+
+lpr_status lpr_step_profiled(lpr_bed* b, int64_t n_steps, double out[4]) {
+  lpr_status g = guard(b);
+  if (g != LPR_OK) return g;
+  if (n_steps < 0 || !out) return fail(LPR_E_INVAL, "bad arguments");
+  for (int c = 0; c < 4; ++c) out[c] = 0.0;
+  if (n_steps == 0) return LPR_OK;
+  std::vector<hipEvent_t> ev((size_t)n_steps * 4);
+  for (auto& e : ev) HIPTRY(hipEventCreate(&e));
+  for (int64_t q = 0; q < n_steps; ++q) {
+    HIPTRY(hipEventRecord(ev[4 * q + 0], b->stream));
+    if (b->since >= b->R) enqueue_rebuild(b);
+    HIPTRY(hipEventRecord(ev[4 * q + 1], b->stream));
+    StepPar p{b->s, b->h, b->l, false};
+    launch_step(b->d, p, b->block, b->record, b->stream);
+    HIPTRY(hipEventRecord(ev[4 * q + 2], b->stream));
+    launch_advance(b->d, b->block, b->stream);
+    HIPTRY(hipEventRecord(ev[4 * q + 3], b->stream));
+    b->s ^= 1;
+    b->h ^= 1;
+    b->since += 1;
+    b->host_steps += 1;
+  }
+  HIPTRY(hipGetLastError());
+  HIPTRY(hipStreamSynchronize(b->stream));
+  for (int64_t q = 0; q < n_steps; ++q) {
+    float ms[3];
+    for (int c = 0; c < 3; ++c) HIPTRY(hipEventElapsedTime(&ms[c], ev[4 * q + c], ev[4 * q + c + 1]));
+    for (int c = 0; c < 3; ++c) out[c] += ms[c];
+  }
+  float tot = 0.f;
+  HIPTRY(hipEventElapsedTime(&tot, ev[0], ev[4 * (n_steps - 1) + 3]));
+  out[3] = tot;
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return sync_check(b);
+}
+
+lpr_status lpr_sync(lpr_bed* b) {
+  if (!b) return fail(LPR_E_INVAL, "null bed");
+  if (b->faulted) return fail(b->fault_status, "latched device fault");
+  return sync_check(b);
+}
+
+lpr_status lpr_get_state(lpr_bed* b, double* pos, float* vel, float* omega) {
+  if (!b) return fail(LPR_E_INVAL, "null bed");
+  int par = 0;
+  lpr_status st = state_parity(b, &par);
+  if (st != LPR_OK) return st;
+  const HostBed& H = b->hb[0];
+  std::vector<double4> hp(H.npad);
+  std::vector<float4> hv(H.npad), hw(H.npad);
+  HIPTRY(hipMemcpy(hp.data(), b->d.pos[par] + H.p0, sizeof(double4) * H.npad, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(hv.data(), b->d.vel[par] + H.p0, sizeof(float4) * H.npad, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(hw.data(), b->d.omg[par] + H.p0, sizeof(float4) * H.npad, hipMemcpyDeviceToHost));
+  for (int64_t off = 0; off < H.n; ++off) {
+    const int64_t q = H.perm[off];
+    if (pos) { pos[3 * q] = hp[off].x; pos[3 * q + 1] = hp[off].y; pos[3 * q + 2] = hp[off].z; }
+    if (vel) { vel[3 * q] = hv[off].x; vel[3 * q + 1] = hv[off].y; vel[3 * q + 2] = hv[off].z; }
+    if (omega) { omega[3 * q] = hw[off].x; omega[3 * q + 1] = hw[off].y; omega[3 * q + 2] = hw[off].z; }
+  }
+  return LPR_OK;
+}
+
+lpr_status lpr_set_state(lpr_bed* b, const double* pos, const float* vel, const float* omega) {
+  lpr_status g = guard(b);
+  if (g != LPR_OK) return g;
+  const HostBed& H = b->hb[0];
+  if (pos && !finite_arr(pos, 3 * H.n)) return fail(LPR_E_INVAL, "non-finite position");
+  if (vel && !finite_arrf(vel, 3 * H.n)) return fail(LPR_E_INVAL, "non-finite velocity");
+  if (omega && !finite_arrf(omega, 3 * H.n)) return fail(LPR_E_INVAL, "non-finite angular velocity");
+  int par = 0;
+  lpr_status st = state_parity(b, &par);
+  if (st != LPR_OK) return st;
+  std::vector<double4> hp(H.npad);
+  std::vector<float4> hv(H.npad), hw(H.npad);
+  HIPTRY(hipMemcpy(hp.data(), b->d.pos[par] + H.p0, sizeof(double4) * H.npad, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(hv.data(), b->d.vel[par] + H.p0, sizeof(float4) * H.npad, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(hw.data(), b->d.omg[par] + H.p0, sizeof(float4) * H.npad, hipMemcpyDeviceToHost));
+  for (int64_t off = 0; off < H.n; ++off) {
+    const int64_t q = H.perm[off];
+    if (pos) { hp[off].x = pos[3 * q]; hp[off].y = pos[3 * q + 1]; hp[off].z = pos[3 * q + 2]; }
+    if (vel) { hv[off].x = vel[3 * q]; hv[off].y = vel[3 * q + 1]; hv[off].z = vel[3 * q + 2]; }
+    if (omega) { hw[off].x = omega[3 * q]; hw[off].y = omega[3 * q + 1]; hw[off].z = omega[3 * q + 2]; }
+  }
+  HIPTRY(hipMemcpy(b->d.pos[par] + H.p0, hp.data(), sizeof(double4) * H.npad, hipMemcpyHostToDevice));
+  HIPTRY(hipMemcpy(b->d.vel[par] + H.p0, hv.data(), sizeof(float4) * H.npad, hipMemcpyHostToDevice));
+  HIPTRY(hipMemcpy(b->d.omg[par] + H.p0, hw.data(), sizeof(float4) * H.npad, hipMemcpyHostToDevice));
+  b->since = std::numeric_limits<int64_t>::max() / 2;  // positions moved: rebuild before the next step
+  return LPR_OK;
+}
+
+lpr_status lpr_get_history(lpr_bed* b, lpr_history* out, int64_t capacity, int64_t* n_total) {
+  if (!b) return fail(LPR_E_INVAL, "null bed");
+  lpr_status st = sync_check(b);
+  if (st != LPR_OK) return st;
+  const HostBed& H = b->hb[0];
+  const int64_t N = b->d.N;
+  std::vector<int32_t> cnt(N), idx((size_t)K * N), sid(N);
+  std::vector<uint32_t> fl(N);
+  std::vector<float4> a((size_t)K * N), wa((size_t)b->max_walls * N);
+  std::vector<float2> c((size_t)K * N), wc((size_t)b->max_walls * N);
+  HIPTRY(hipMemcpy(cnt.data(), b->d.own_cnt[b->l], sizeof(int32_t) * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(idx.data(), b->d.own_idx[b->l], sizeof(int32_t) * K * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(sid.data(), b->d.sid, sizeof(int32_t) * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(fl.data(), b->d.cflag[b->h], sizeof(uint32_t) * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(a.data(), b->d.hA[b->h], sizeof(float4) * K * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(c.data(), b->d.hB[b->h], sizeof(float2) * K * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(wa.data(), b->d.wA[b->h], sizeof(float4) * b->max_walls * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(wc.data(), b->d.wB[b->h], sizeof(float2) * b->max_walls * N, hipMemcpyDeviceToHost));
+  std::vector<lpr_history> recs;
+  for (int64_t i = H.p0; i < H.p0 + H.npad; ++i) {
+    if (sid[i] < 0) continue;
+    for (int k = 0; k < cnt[i]; ++k)
+      if ((fl[i] >> k) & 1u) {
+        const float4 A = a[(size_t)k * N + i];
+        const float2 C = c[(size_t)k * N + i];
+        recs.push_back({sid[i], sid[idx[(size_t)k * N + i]], {A.x, A.y, A.z}, {A.w, C.x, C.y}});
+      }
+    for (int w = 0; w < H.nwall; ++w)
+      if ((fl[i] >> (WALL_BIT + w)) & 1u) {
+        const float4 A = wa[(size_t)w * N + i];
+        const float2 C = wc[(size_t)w * N + i];
+        recs.push_back({sid[i], -1 - (int64_t)w, {A.x, A.y, A.z}, {A.w, C.x, C.y}});
+      }
+  }
+  std::sort(recs.begin(), recs.end(), [](const lpr_history& x, const lpr_history& y) {
+    return x.owner < y.owner || (x.owner == y.owner && x.partner < y.partner);
+  });
+  if (n_total) *n_total = (int64_t)recs.size();
+  if ((int64_t)recs.size() > capacity) return fail(LPR_E_CAPACITY, "history buffer too small");
+  if (!recs.empty()) std::memcpy(out, recs.data(), sizeof(lpr_history) * recs.size());
+  return LPR_OK;
+}
+
+lpr_status lpr_set_history(lpr_bed* b, const lpr_history* rec, int64_t count) {
+  lpr_status g = guard(b);
+  if (g != LPR_OK) return g;
+  if (count < 0 || (count > 0 && !rec)) return fail(LPR_E_INVAL, "bad history records");
+  ensure_lists(b);
+  lpr_status st = sync_check(b);
+  if (st != LPR_OK) return st;
+  const HostBed& H = b->hb[0];
+  const int64_t N = b->d.N;
+  std::vector<int32_t> cnt(N), idx((size_t)K * N), sid(N);
+  HIPTRY(hipMemcpy(cnt.data(), b->d.own_cnt[b->l], sizeof(int32_t) * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(idx.data(), b->d.own_idx[b->l], sizeof(int32_t) * K * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(sid.data(), b->d.sid, sizeof(int32_t) * N, hipMemcpyDeviceToHost));
+  std::vector<std::vector<const lpr_history*>> by_owner(H.n);
+  for (int64_t q = 0; q < count; ++q) {
+    if (rec[q].owner < 0 || rec[q].owner >= H.n) return fail(LPR_E_INVAL, "history owner out of range");
+    by_owner[rec[q].owner].push_back(&rec[q]);
+  }
+  std::vector<uint32_t> fl(N, 0u);
+  std::vector<float4> a((size_t)K * N, make_float4(0, 0, 0, 0)), wa((size_t)b->max_walls * N, make_float4(0, 0, 0, 0));
+  std::vector<float2> c((size_t)K * N, make_float2(0, 0)), wc((size_t)b->max_walls * N, make_float2(0, 0));
+  for (int64_t i = H.p0; i < H.p0 + H.npad; ++i) {
+    if (sid[i] < 0) continue;
+    for (const lpr_history* r : by_owner[sid[i]]) {
+      if (r->partner >= 0) {
+        for (int k = 0; k < cnt[i]; ++k)
+          if (sid[idx[(size_t)k * N + i]] == r->partner) {
+            a[(size_t)k * N + i] = make_float4(r->xi_t[0], r->xi_t[1], r->xi_t[2], r->xi_r[0]);
+            c[(size_t)k * N + i] = make_float2(r->xi_r[1], r->xi_r[2]);
+            fl[i] |= 1u << k;
+          }
+      } else {
+        const int64_t w = -1 - r->partner;
+        if (w < H.nwall) {
+          wa[(size_t)w * N + i] = make_float4(r->xi_t[0], r->xi_t[1], r->xi_t[2], r->xi_r[0]);
+          wc[(size_t)w * N + i] = make_float2(r->xi_r[1], r->xi_r[2]);
+          fl[i] |= 1u << (WALL_BIT + w);
+        }
+      }
+    }
+  }
+  HIPTRY(hipMemcpy(b->d.cflag[b->h], fl.data(), sizeof(uint32_t) * N, hipMemcpyHostToDevice));
+  HIPTRY(hipMemcpy(b->d.hA[b->h], a.data(), sizeof(float4) * K * N, hipMemcpyHostToDevice));
+  HIPTRY(hipMemcpy(b->d.hB[b->h], c.data(), sizeof(float2) * K * N, hipMemcpyHostToDevice));
+  HIPTRY(hipMemcpy(b->d.wA[b->h], wa.data(), sizeof(float4) * b->max_walls * N, hipMemcpyHostToDevice));
+  HIPTRY(hipMemcpy(b->d.wB[b->h], wc.data(), sizeof(float2) * b->max_walls * N, hipMemcpyHostToDevice));
+  return LPR_OK;
+}
+
+lpr_status lpr_read_contacts(lpr_bed* b, lpr_contact* out, int64_t capacity, int64_t* n_total) {
+  if (!b) return fail(LPR_E_INVAL, "null bed");
+  lpr_status st = sync_check(b);
+  if (st != LPR_OK) return st;
+  const HostBed& H = b->hb[0];
+  const int64_t N = b->d.N;
+  std::vector<int32_t> cnt(N), idx((size_t)K * N), sid(N);
+  std::vector<uint32_t> fl(N);
+  HIPTRY(hipMemcpy(cnt.data(), b->d.own_cnt[b->l], sizeof(int32_t) * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(idx.data(), b->d.own_idx[b->l], sizeof(int32_t) * K * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(sid.data(), b->d.sid, sizeof(int32_t) * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(fl.data(), b->d.cflag[b->h], sizeof(uint32_t) * N, hipMemcpyDeviceToHost));
+  std::vector<lpr_contact> cs;
+  if (b->host_steps > 0) {
+    for (int64_t i = H.p0; i < H.p0 + H.npad; ++i) {
+      if (sid[i] < 0) continue;
+      for (int k = 0; k < cnt[i]; ++k)
+        if ((fl[i] >> k) & 1u) {
+          const int64_t x = sid[i], y = sid[idx[(size_t)k * N + i]];
+          cs.push_back({std::min(x, y), std::max(x, y)});
+        }
+      for (int w = 0; w < H.nwall; ++w)
+        if ((fl[i] >> (WALL_BIT + w)) & 1u) cs.push_back({(int64_t)sid[i], -1 - (int64_t)w});
+    }
+  }
+  std::sort(cs.begin(), cs.end(),
+            [](const lpr_contact& x, const lpr_contact& y) { return x.a < y.a || (x.a == y.a && x.b < y.b); });
+  if (n_total) *n_total = (int64_t)cs.size();
+  if ((int64_t)cs.size() > capacity) return fail(LPR_E_CAPACITY, "contact buffer too small");
+  if (!cs.empty()) std::memcpy(out, cs.data(), sizeof(lpr_contact) * cs.size());
+  return LPR_OK;
+}
+
+lpr_status lpr_read_forces(lpr_bed* b, float* force, float* torque) {
+  if (!b) return fail(LPR_E_INVAL, "null bed");
+  if (!b->record) return fail(LPR_E_STATE, "bed was created without record_forces");
+  lpr_status st = sync_check(b);
+  if (st != LPR_OK) return st;
+  const HostBed& H = b->hb[0];
+  std::vector<float4> f(H.npad), t(H.npad);
+  HIPTRY(hipMemcpy(f.data(), b->d.frc + H.p0, sizeof(float4) * H.npad, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(t.data(), b->d.trq + H.p0, sizeof(float4) * H.npad, hipMemcpyDeviceToHost));
+  for (int64_t off = 0; off < H.n; ++off) {
+    const int64_t q = H.perm[off];
+    if (force) { force[3 * q] = f[off].x; force[3 * q + 1] = f[off].y; force[3 * q + 2] = f[off].z; }
+    if (torque) { torque[3 * q] = t[off].x; torque[3 * q + 1] = t[off].y; torque[3 * q + 2] = t[off].z; }
+  }
+  return LPR_OK;
+}
+
+lpr_status lpr_read_reaction(lpr_bed* b, int32_t body, double out6[6]) {
+  if (!b || !out6) return fail(LPR_E_INVAL, "null argument");
+  const HostBed& H = b->hb[0];
+  if (body < 0 || body >= H.nbody) return fail(LPR_E_INVAL, "body out of range");
+  lpr_status st = sync_check(b);
+  if (st != LPR_OK) return st;
+  BodyDyn D;
+  HIPTRY(hipMemcpy(&D, b->d.bdyn + H.body0 + body, sizeof(BodyDyn), hipMemcpyDeviceToHost));
+  for (int c = 0; c < 6; ++c) out6[c] = D.last[c];
+  return LPR_OK;
+}
+
+lpr_status lpr_reaction_window(lpr_bed* b, int32_t body, double sum6[6], int64_t* steps, int32_t reset) {
+  if (!b) return fail(LPR_E_INVAL, "null bed");
+  const HostBed& H = b->hb[0];
+  if (body < 0 || body >= H.nbody) return fail(LPR_E_INVAL, "body out of range");
+  lpr_status st = sync_check(b);
+  if (st != LPR_OK) return st;
+  BodyDyn D;
+  HIPTRY(hipMemcpy(&D, b->d.bdyn + H.body0 + body, sizeof(BodyDyn), hipMemcpyDeviceToHost));
+  if (sum6)
+    for (int c = 0; c < 6; ++c) sum6[c] = D.wsum[c];
+  if (steps) *steps = D.wsteps;
+  if (reset) {
+    for (int c = 0; c < 6; ++c) D.wsum[c] = 0.0;
+    D.wsteps = 0;
+    HIPTRY(hipMemcpy(b->d.bdyn + H.body0 + body, &D, sizeof(BodyDyn), hipMemcpyHostToDevice));
+  }
+  return LPR_OK;
+}
+
+lpr_status lpr_read_body(lpr_bed* b, int32_t body, double origin[3], double vel[3]) {
+  if (!b) return fail(LPR_E_INVAL, "null bed");
+  const HostBed& H = b->hb[0];
+  if (body < 0 || body >= H.nbody) return fail(LPR_E_INVAL, "body out of range");
+  HIPTRY(hipStreamSynchronize(b->stream));
+  BodyDyn D;
+  BodyDef B;
+  BedDyn E;
+  HIPTRY(hipMemcpy(&D, b->d.bdyn + H.body0 + body, sizeof(BodyDyn), hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(&B, b->d.bdefs + H.body0 + body, sizeof(BodyDef), hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(&E, b->d.bedyn, sizeof(BedDyn), hipMemcpyDeviceToHost));
+  const double t = (double)E.k * H.dt;
+  for (int a = 0; a < 3; ++a) {
+    if (origin) origin[a] = B.origin[a] + B.lin_vel[a] * t;
+    if (vel) vel[a] = B.lin_vel[a];
+  }
+  if (B.z_free) {
+    if (origin) origin[2] = D.z;
+    if (vel) vel[2] = D.vz;
+  }
+  return LPR_OK;
+}
+
+lpr_status lpr_set_clock(lpr_bed* b, int64_t step) {
+  lpr_status g = guard(b);
+  if (g != LPR_OK) return g;
+  if (step < 0) return fail(LPR_E_INVAL, "step must be >= 0");
+  HIPTRY(hipStreamSynchronize(b->stream));
+  BedDyn E;
+  HIPTRY(hipMemcpy(&E, b->d.bedyn, sizeof(BedDyn), hipMemcpyDeviceToHost));
+  E.k = step;
+  HIPTRY(hipMemcpy(b->d.bedyn, &E, sizeof(BedDyn), hipMemcpyHostToDevice));
+  launch_poses(b->d, b->stream);
+  HIPTRY(hipStreamSynchronize(b->stream));
+  return LPR_OK;
+}
+
+lpr_status lpr_get_clock(lpr_bed* b, int64_t* step) {
+  if (!b || !step) return fail(LPR_E_INVAL, "null argument");
+  HIPTRY(hipStreamSynchronize(b->stream));
+  BedDyn E;
+  HIPTRY(hipMemcpy(&E, b->d.bedyn, sizeof(BedDyn), hipMemcpyDeviceToHost));
+  *step = E.k;
+  return LPR_OK;
+}
+
+lpr_status lpr_set_body_state(lpr_bed* b, int32_t body, double z, double vz) {
+  lpr_status g = guard(b);
+  if (g != LPR_OK) return g;
+  const HostBed& H = b->hb[0];
+  if (body < 0 || body >= H.nbody) return fail(LPR_E_INVAL, "body out of range");
+  HIPTRY(hipStreamSynchronize(b->stream));
+  BodyDyn D;
+  HIPTRY(hipMemcpy(&D, b->d.bdyn + H.body0 + body, sizeof(BodyDyn), hipMemcpyDeviceToHost));
+  D.z = z;
+  D.vz = vz;
+  HIPTRY(hipMemcpy(b->d.bdyn + H.body0 + body, &D, sizeof(BodyDyn), hipMemcpyHostToDevice));
+  launch_poses(b->d, b->stream);
+  HIPTRY(hipStreamSynchronize(b->stream));
+  return LPR_OK;
+}
+
+lpr_status lpr_get_stats(lpr_bed* b, lpr_stats* out) {
+  if (!b || !out) return fail(LPR_E_INVAL, "null argument");
+  HIPTRY(hipStreamSynchronize(b->stream));
+  BedDyn E;
+  uint32_t stat[4];
+  HIPTRY(hipMemcpy(&E, b->d.bedyn, sizeof(BedDyn), hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(stat, b->d.stat, sizeof(stat), hipMemcpyDeviceToHost));
+  const int64_t N = b->d.N;
+  std::vector<int32_t> cnt(N);
+  std::vector<uint32_t> fl(N);
+  HIPTRY(hipMemcpy(cnt.data(), b->d.own_cnt[b->l], sizeof(int32_t) * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(fl.data(), b->d.cflag[b->h], sizeof(uint32_t) * N, hipMemcpyDeviceToHost));
+  int64_t cand = 0, con = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    cand += cnt[i];
+    con += __builtin_popcount(fl[i]);
+  }
+  out->steps = E.completed;
+  out->contacts = b->host_steps > 0 ? con : 0;
+  out->candidates = cand;
+  out->rebuilds = b->rebuilds;
+  out->levels = b->nlev_total;
+  out->cells = b->ncells;
+  out->max_owner_slots = (int32_t)stat[0];
+  return LPR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,359 @@
+"""Python binding of the HIP stepper (include/lprdem.h).
+
+Argument marshalling only: every step of the pipeline runs in the HIP
+library paper_2501_05300_amd/liblprdem.so.  PyTorch supplies device memory
+(its caching allocator, through the library's allocator callbacks) and the
+HIP stream.  There is no CPU fallback: constructing a Bed without the built
+library or without a GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblprdem.so")
+
+SLOTS = 16
+MAX_WALLS = 16
+MAX_BODIES = 4
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error", -4: "capacity exceeded",
+          -5: "invalid state", -6: "non-finite value"}
+
+# Entry points declared in include/lprdem.h
+SYMBOLS = ("lpr_bed_create", "lpr_bed_destroy", "lpr_step", "lpr_step_profiled", "lpr_sync", "lpr_get_state", "lpr_set_state",
+           "lpr_get_history", "lpr_set_history", "lpr_read_contacts", "lpr_read_forces", "lpr_read_reaction",
+           "lpr_reaction_window", "lpr_read_body", "lpr_set_clock", "lpr_get_clock", "lpr_set_body_state",
+           "lpr_get_stats", "lpr_status_str", "lpr_last_error")
+
+
+class LprError(RuntimeError):
+    def __init__(self, status, where, message):
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({message})")
+        self.status = status
+
+
+class CapacityError(LprError):
+    pass
+
+
+class NumericError(LprError):
+    pass
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_double), ("E", ctypes.c_double), ("nu", ctypes.c_double),
+                ("mu_t", ctypes.c_double), ("mu_r", ctypes.c_double), ("dt", ctypes.c_double),
+                ("gamma_factor", ctypes.c_double), ("e_H", ctypes.c_double), ("kappa_t", ctypes.c_double),
+                ("s_k", ctypes.c_double), ("g", ctypes.c_double * 3)]
+
+
+class _Wall(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("body", ctypes.c_int32), ("origin", ctypes.c_double * 3),
+                ("axis", ctypes.c_double * 3), ("frame", ctypes.c_double * 9), ("dims", ctypes.c_double * 3),
+                ("mu_t", ctypes.c_double), ("mu_r", ctypes.c_double)]
+
+
+class _Body(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_double * 3), ("lin_vel", ctypes.c_double * 3), ("ang_vel", ctypes.c_double),
+                ("z_free", ctypes.c_int32), ("mass", ctypes.c_double)]
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("box", ctypes.c_double * 3), ("periodic", ctypes.c_uint32),
+                ("pos", ctypes.c_void_p), ("radius", ctypes.c_void_p), ("vel", ctypes.c_void_p),
+                ("omega", ctypes.c_void_p), ("n_walls", ctypes.c_int32), ("walls", ctypes.c_void_p),
+                ("n_bodies", ctypes.c_int32), ("bodies", ctypes.c_void_p), ("params", _Params),
+                ("rebuild_every", ctypes.c_int32), ("skin", ctypes.c_float), ("band_ratio", ctypes.c_float),
+                ("cell_factor", ctypes.c_float), ("block", ctypes.c_int32), ("record_forces", ctypes.c_int32)]
+
+
+_ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+_RELEASE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC), ("release", _RELEASE), ("ctx", ctypes.c_void_p)]
+
+
+class _Contact(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_int64), ("b", ctypes.c_int64)]
+
+
+class _History(ctypes.Structure):
+    _fields_ = [("owner", ctypes.c_int64), ("partner", ctypes.c_int64), ("xi_t", ctypes.c_float * 3),
+                ("xi_r", ctypes.c_float * 3)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("contacts", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                ("rebuilds", ctypes.c_int64), ("levels", ctypes.c_int32), ("cells", ctypes.c_int64),
+                ("max_owner_slots", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads liblprdem.so (importing torch first so that the process shares
+    one HIP runtime).  Raises if the library is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is not built; run __graft_entry__.build()")
+    import torch  # noqa: F401  (brings torch's HIP runtime into the process first)
+    L = ctypes.CDLL(path)
+    vp, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "lpr_bed_create": [ctypes.POINTER(_Desc), ctypes.POINTER(_Allocator), vp, ctypes.POINTER(vp)],
+        "lpr_bed_destroy": [vp], "lpr_step": [vp, i64], "lpr_sync": [vp],
+        "lpr_step_profiled": [vp, i64, vp],
+        "lpr_get_state": [vp, vp, vp, vp], "lpr_set_state": [vp, vp, vp, vp],
+        "lpr_get_history": [vp, vp, i64, ctypes.POINTER(i64)], "lpr_set_history": [vp, vp, i64],
+        "lpr_read_contacts": [vp, vp, i64, ctypes.POINTER(i64)], "lpr_read_forces": [vp, vp, vp],
+        "lpr_read_reaction": [vp, i32, vp], "lpr_reaction_window": [vp, i32, vp, ctypes.POINTER(i64), i32],
+        "lpr_read_body": [vp, i32, vp, vp], "lpr_set_clock": [vp, i64], "lpr_get_clock": [vp, ctypes.POINTER(i64)],
+        "lpr_set_body_state": [vp, i32, d, d], "lpr_get_stats": [vp, ctypes.POINTER(_Stats)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.restype = ctypes.c_int
+        f.argtypes = args
+    L.lpr_status_str.restype = ctypes.c_char_p
+    L.lpr_status_str.argtypes = [ctypes.c_int]
+    L.lpr_last_error.restype = ctypes.c_char_p
+    L.lpr_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(rc, where):
+    if rc == 0:
+        return
+    msg = _lib.lpr_last_error().decode(errors="replace") if _lib is not None else ""
+    if rc == -4:
+        raise CapacityError(rc, where, msg)
+    if rc == -6:
+        raise NumericError(rc, where, msg)
+    raise LprError(rc, where, msg)
+
+
+def params_struct(p) -> _Params:
+    q = _Params()
+    for f in ("rho", "E", "nu", "mu_t", "mu_r", "dt", "gamma_factor", "e_H", "kappa_t", "s_k"):
+        setattr(q, f, float(getattr(p, f)))
+    for a in range(3):
+        q.g[a] = float(p.g[a])
+    return q
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+class _DescHolder:
+    """A filled lpr_bed_desc plus the arrays it points to (kept alive)."""
+
+    def __init__(self, spec, rebuild_every, skin, band_ratio, cell_factor, block, record_forces):
+        self.pos = np.ascontiguousarray(spec.pos, np.float64)
+        self.rad = np.ascontiguousarray(spec.radius, np.float32)
+        self.vel = np.ascontiguousarray(spec.vel, np.float32)
+        self.omg = np.ascontiguousarray(spec.omega, np.float32)
+        nw, nb = len(spec.walls), len(spec.bodies)
+        self.walls = (_Wall * max(1, nw))()
+        for q, w in enumerate(spec.walls):
+            W = self.walls[q]
+            W.kind, W.body = int(w.kind), int(w.body)
+            for a in range(3):
+                W.origin[a], W.axis[a], W.dims[a] = w.origin[a], w.axis[a], w.dims[a]
+            for a in range(9):
+                W.frame[a] = w.frame[a]
+            W.mu_t, W.mu_r = float(w.mu_t), float(w.mu_r)
+        self.bodies = (_Body * max(1, nb))()
+        for q, b in enumerate(spec.bodies):
+            B = self.bodies[q]
+            for a in range(3):
+                B.origin[a], B.lin_vel[a] = b.origin[a], b.lin_vel[a]
+            B.ang_vel, B.z_free, B.mass = float(b.ang_vel), int(b.z_free), float(b.mass)
+        D = _Desc()
+        D.n = spec.n
+        for a in range(3):
+            D.box[a] = float(spec.box[a])
+        D.periodic = int(spec.periodic)
+        D.pos, D.radius = self.pos.ctypes.data, self.rad.ctypes.data
+        D.vel, D.omega = self.vel.ctypes.data, self.omg.ctypes.data
+        D.n_walls, D.walls = nw, ctypes.addressof(self.walls)
+        D.n_bodies, D.bodies = nb, ctypes.addressof(self.bodies)
+        D.params = params_struct(spec.params)
+        D.rebuild_every = int(rebuild_every)
+        D.skin = float(skin)
+        D.band_ratio = float(band_ratio)
+        D.cell_factor = float(cell_factor)
+        D.block = int(block)
+        D.record_forces = 1 if record_forces else 0
+        self.desc = D
+
+
+class Bed:
+    """A graded bed stepped by the HIP library on one GPU.
+
+    spec: paper_2501_05300_amd.beds.BedSpec.  rebuild_every / skin /
+    band_ratio / cell_factor / block choose how contacts are found (never
+    which); record_forces keeps per-particle contact forces for forces().
+    """
+
+    def __init__(self, spec, rebuild_every=1, skin=0.0, band_ratio=0.0, cell_factor=0.0, block=0,
+                 record_forces=False, device=0, torch_memory=True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP stepper needs a GPU (torch.cuda.is_available() is False)")
+        L = load_library()
+        self.spec = spec
+        self.n = spec.n
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.Stream(self.device)
+        self._holder = _DescHolder(spec, rebuild_every, skin, band_ratio, cell_factor, block, record_forces)
+        self._live = {}
+        dev, stream = self.device, self.stream
+
+        def _alloc(ctx, nbytes):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+            except Exception:  # noqa: BLE001  (reported to the library as NULL)
+                return None
+            self._live[p] = nbytes
+            return p
+
+        def _release(ctx, p):
+            if p in self._live:
+                del self._live[p]
+                torch.cuda.caching_allocator_delete(p)
+
+        self._cb = (_ALLOC(_alloc), _RELEASE(_release))
+        self._alloc = _Allocator(self._cb[0], self._cb[1], None)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = L.lpr_bed_create(ctypes.byref(self._holder.desc),
+                                  ctypes.byref(self._alloc) if torch_memory else None,
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        _check(rc, "lpr_bed_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lpr_bed_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    # stepping
+    def step(self, n=1):
+        _check(_lib.lpr_step(self._h, int(n)), "lpr_step")
+
+    def step_profiled(self, n):
+        """Steps n times with HIP events around each kernel group; returns
+        summed milliseconds {rebuild, step, advance, total}."""
+        out = np.zeros(4)
+        _check(_lib.lpr_step_profiled(self._h, int(n), _ptr(out)), "lpr_step_profiled")
+        return {"rebuild": out[0], "step": out[1], "advance": out[2], "total": out[3]}
+
+    def sync(self):
+        _check(_lib.lpr_sync(self._h), "lpr_sync")
+
+    # state
+    def state(self):
+        pos = np.zeros((self.n, 3), np.float64)
+        vel = np.zeros((self.n, 3), np.float32)
+        omg = np.zeros((self.n, 3), np.float32)
+        _check(_lib.lpr_get_state(self._h, _ptr(pos), _ptr(vel), _ptr(omg)), "lpr_get_state")
+        return pos, vel, omg
+
+    def set_state(self, pos=None, vel=None, omg=None):
+        c64 = lambda a: None if a is None else np.ascontiguousarray(a, np.float64).reshape(-1, 3)
+        c32 = lambda a: None if a is None else np.ascontiguousarray(a, np.float32).reshape(-1, 3)
+        pos, vel, omg = c64(pos), c32(vel), c32(omg)
+        _check(_lib.lpr_set_state(self._h, _ptr(pos), _ptr(vel), _ptr(omg)), "lpr_set_state")
+
+    def history(self):
+        """(keys (k, 2) int64 owner/partner code, values (k, 6) float32)."""
+        tot = ctypes.c_int64(0)
+        rc = _lib.lpr_get_history(self._h, None, 0, ctypes.byref(tot))
+        if rc not in (0, -4):
+            _check(rc, "lpr_get_history")
+        buf = (_History * max(1, tot.value))()
+        _check(_lib.lpr_get_history(self._h, ctypes.addressof(buf), tot.value, ctypes.byref(tot)),
+               "lpr_get_history")
+        arr = np.frombuffer(buf, dtype=np.dtype([("o", "<i8"), ("p", "<i8"), ("v", "<f4", (6,))]),
+                            count=tot.value)
+        return np.stack([arr["o"], arr["p"]], 1), arr["v"].copy()
+
+    def set_history(self, keys, vals):
+        keys = np.asarray(keys, np.int64).reshape(-1, 2)
+        vals = np.asarray(vals, np.float32).reshape(-1, 6)
+        buf = (_History * max(1, len(keys)))()
+        for q in range(len(keys)):
+            buf[q].owner, buf[q].partner = int(keys[q, 0]), int(keys[q, 1])
+            for a in range(3):
+                buf[q].xi_t[a] = float(vals[q, a])
+                buf[q].xi_r[a] = float(vals[q, 3 + a])
+        _check(_lib.lpr_set_history(self._h, ctypes.addressof(buf), len(keys)), "lpr_set_history")
+
+    # results of the last step
+    def contacts(self):
+        """(k, 2) int64: particle pairs (a < b stable ids) and wall contacts
+        (particle, -1 - wall), ascending."""
+        tot = ctypes.c_int64(0)
+        rc = _lib.lpr_read_contacts(self._h, None, 0, ctypes.byref(tot))
+        if rc not in (0, -4):
+            _check(rc, "lpr_read_contacts")
+        out = np.zeros((max(1, tot.value), 2), np.int64)
+        _check(_lib.lpr_read_contacts(self._h, _ptr(out), tot.value, ctypes.byref(tot)), "lpr_read_contacts")
+        return out[:tot.value]
+
+    def forces(self):
+        F = np.zeros((self.n, 3), np.float32)
+        T = np.zeros((self.n, 3), np.float32)
+        _check(_lib.lpr_read_forces(self._h, _ptr(F), _ptr(T)), "lpr_read_forces")
+        return F, T
+
+    def reaction(self, body):
+        out = np.zeros(6)
+        _check(_lib.lpr_read_reaction(self._h, int(body), _ptr(out)), "lpr_read_reaction")
+        return out
+
+    def reaction_window(self, body, reset=False):
+        s = np.zeros(6)
+        k = ctypes.c_int64(0)
+        _check(_lib.lpr_reaction_window(self._h, int(body), _ptr(s), ctypes.byref(k), 1 if reset else 0),
+               "lpr_reaction_window")
+        return s, k.value
+
+    def body(self, body):
+        o = np.zeros(3)
+        v = np.zeros(3)
+        _check(_lib.lpr_read_body(self._h, int(body), _ptr(o), _ptr(v)), "lpr_read_body")
+        return o, v
+
+    def set_clock(self, step):
+        _check(_lib.lpr_set_clock(self._h, int(step)), "lpr_set_clock")
+
+    def clock(self):
+        k = ctypes.c_int64(0)
+        _check(_lib.lpr_get_clock(self._h, ctypes.byref(k)), "lpr_get_clock")
+        return k.value
+
+    def set_body_state(self, body, z, vz):
+        _check(_lib.lpr_set_body_state(self._h, int(body), float(z), float(vz)), "lpr_set_body_state")
+
+    def stats(self):
+        s = _Stats()
+        _check(_lib.lpr_get_stats(self._h, ctypes.byref(s)), "lpr_get_stats")
+        return {f: getattr(s, f) for f, _ in _Stats._fields_}

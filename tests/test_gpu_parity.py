@@ -1,0 +1,153 @@
+"""Parity of the HIP stepper with the FP64 oracle (GPU).
+
+Bars: contact lists bit-exact given the same state; per-step contact forces
+and torques within 1e-5 (normwise over particles); body reactions within
+1e-5; short trajectories within 1e-3 r_min after 1000 steps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2501_05300_amd import beds
+from parity_util import compare_one_step, masses, oracle_pairs, rel_norm
+
+pytestmark = pytest.mark.gpu
+
+FTOL = 1e-5
+
+
+def gpu_bed(spec, **kw):
+    from paper_2501_05300_amd.lprdem import Bed
+    kw.setdefault("record_forces", True)
+    return Bed(spec, **kw)
+
+
+def cloud(seed, n=3000, side=0.04, periodic=3, walls=True, ratio=10.0, vel=0.05, omg=20.0, E=1e7):
+    prm = beds.Params(E=E)
+    spec = beds.random_cloud(n, side, 0.03, 0.5e-3, 0.5e-3 * ratio, seed=seed, periodic=periodic, params=prm,
+                             vel_scale=vel, omega_scale=omg)
+    if walls:
+        spec.walls = [beds.floor_wall(),
+                      beds.Wall(kind=beds.WALL_DISK, body=1, axis=(0, 0, -1), dims=(0.01, 0, 0)),
+                      beds.Wall(kind=beds.WALL_BOX, body=1, origin=(0.0, 0.012, 0.0), dims=(0.004, 0.002, 0.003))]
+        spec.bodies = [beds.Body(), beds.Body(origin=(0.5 * side, 0.5 * side, 0.02), lin_vel=(0.0, 0.0, -0.05))]
+    return spec
+
+
+@pytest.mark.parametrize("seed,periodic", [(1, 3), (2, 0), (3, 1)])
+def test_first_step_matches_oracle(seed, periodic):
+    spec = cloud(seed, periodic=periodic)
+    bed = gpu_bed(spec)
+    res = compare_one_step(spec, bed)
+    print(res)
+    assert res["contacts_equal"], res
+    assert res["n_contacts"] > 500
+    assert res["force_rel"] < FTOL and res["torque_rel"] < FTOL
+    assert res["reaction0_rel"] < FTOL and res["reaction1_rel"] < FTOL
+
+
+def test_two_layer_bed_history_parity():
+    """Two-layer bed (2,000 spheres): after 300 GPU steps the state and
+    contact history are handed to the oracle; the next step must agree."""
+    spec = beds.two_layer_bed(0)
+    bed = gpu_bed(spec)
+    bed.step(300)
+    keys, _ = bed.history()
+    assert len(keys) > 1000
+    for _ in range(3):
+        res = compare_one_step(spec, bed)
+        print(res)
+        assert res["contacts_equal"], res
+        assert res["force_rel"] < FTOL and res["torque_rel"] < FTOL
+        assert res["reaction0_rel"] < FTOL
+        bed.step(50)
+
+
+def test_static_columns_balance_gravity_gpu():
+    from test_oracle_pins import static_columns
+    spec = static_columns()
+    bed = gpu_bed(spec)
+    bed.step(1)
+    m, _ = masses(spec)
+    F, T = bed.forces()
+    np.testing.assert_allclose(F[:, 2], m * 9.81, rtol=2e-5)
+    R = bed.reaction(0)
+    W = m.sum() * 9.81
+    assert abs(R[2] + W) < 2e-5 * W
+    assert len(bed.contacts()) == spec.n
+
+
+def test_momentum_conserved_gpu():
+    spec = cloud(5, walls=False, vel=0.05, omg=20.0)
+    spec.params = spec.params.replace(g=(0.0, 0.0, 0.0))
+    bed = gpu_bed(spec)
+    m, _ = masses(spec)
+    _, v0, _ = bed.state()
+    P0 = (m[:, None] * v0).sum(0)
+    bed.step(1000)
+    _, v1, _ = bed.state()
+    P1 = (m[:, None] * v1.astype(np.float64)).sum(0)
+    scale = (m * np.linalg.norm(v1, axis=1)).sum()
+    assert np.all(np.abs(P1 - P0) < 1e-6 * scale)
+
+
+def test_bitwise_determinism_and_graph_replay():
+    """Two beds from the same input give bitwise equal states; stepping by
+    captured-graph cycles equals stepping one step at a time."""
+    spec = beds.two_layer_bed(1)
+    a, b = gpu_bed(spec), gpu_bed(spec)
+    a.step(40)                 # graph cycles
+    for _ in range(40):
+        b.step(1)              # direct launches
+    xa, va, wa = a.state()
+    xb, vb, wb = b.state()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb) and np.array_equal(wa, wb)
+    assert np.array_equal(a.contacts(), b.contacts())
+
+
+def test_short_trajectory_bound():
+    """Two-layer bed, 1000 steps from the same state: the FP32 stepper stays
+    within 1e-3 r_min of the FP64 oracle."""
+    spec = beds.two_layer_bed(2)
+    bed = gpu_bed(spec, record_forces=False)
+    ob = O.OracleBed(spec)
+    bed.step(1000)
+    ob.step(1000)
+    xg, _, _ = bed.state()
+    xo, _, _ = ob.state()
+    d = xg - xo
+    L = spec.box[0]
+    d[:, :2] -= L * np.round(d[:, :2] / L)
+    err = np.linalg.norm(d, axis=1).max()
+    print("max trajectory deviation", err)
+    assert err < 1e-3 * float(spec.radius.min())
+
+
+@pytest.mark.parametrize("opts", [dict(cell_factor=1.5), dict(band_ratio=1.5), dict(block=64), dict(block=128),
+                                  dict(band_ratio=8.0, cell_factor=1.25)])
+def test_contact_list_invariant_to_broad_phase_choices(opts):
+    spec = cloud(9, n=2500)
+    ref = gpu_bed(spec)
+    ref.step(1)
+    alt = gpu_bed(spec, **opts)
+    alt.step(1)
+    assert np.array_equal(ref.contacts(), alt.contacts())
+    Fr, _ = ref.forces()
+    Fa, _ = alt.forces()
+    assert rel_norm(Fa, Fr) < 1e-6
+
+
+def test_plate_reaction_parity():
+    """Two-layer bed with a plate pushed into it: plate reaction within 1e-5."""
+    spec = beds.add_plate(beds.two_layer_bed(3), diameter=0.04, speed=0.05)
+    bed = gpu_bed(spec)
+    bed.step(400)
+    res = compare_one_step(spec, bed)
+    print(res)
+    assert res["contacts_equal"], res
+    assert res["force_rel"] < FTOL
+    R = bed.reaction(1)
+    assert abs(R[2]) > 0
+    assert res["reaction1_rel"] < FTOL
