@@ -62,6 +62,35 @@ def counter_traffic(n_particles):
     return c.get("hbm_bytes_per_launch")
 
 
+def settle_bed(spec, steps, chunk=2000):
+    """Relaxes the deposited bed in place (positions only) with the paper's
+    relaxation friction (mu_t 0.1, mu_r 0.01, frictionless walls), extra
+    normal damping (gamma_n = 50 dt) and dt = 5e-6 s; velocities are then
+    zeroed.  Untimed preparation of the input."""
+    import numpy as np
+    from paper_2501_05300_amd import beds
+    from paper_2501_05300_amd.lprdem import Bed
+    s = spec.copy()
+    s.params = beds.settle_params(spec.params).replace(dt=5e-6, gamma_factor=50.0)
+    for w in s.walls:
+        w.mu_t, w.mu_r = 0.0, 0.0
+    sb = Bed(s, rebuild_every=1)
+    done = 0
+    t0 = time.perf_counter()
+    while done < steps:
+        k = min(chunk, steps - done)
+        sb.step(k)
+        sb.sync()
+        done += k
+        st = sb.stats()
+        log(f"settle {done}/{steps}: contacts/particle {st['contacts'] / spec.n:.3f} ({time.perf_counter() - t0:.1f} s)")
+    pos, _, _ = sb.state()
+    sb.close()
+    spec.pos = pos
+    spec.vel = np.zeros_like(spec.vel)
+    spec.omega = np.zeros_like(spec.omega)
+
+
 def cpu_baseline(spec, pos, vel, omg, keys, vals, clock, steps):
     """The FP64 oracle, as it stands, on the same bed state (bounded sample:
     `steps` steps of the full bed)."""
@@ -91,6 +120,8 @@ def main():
     ap.add_argument("--skin", type=float, default=0.0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--settle", type=int, default=20000,
+                    help="relaxation steps before the measurement (paper's reduced friction, damped, dt 5e-6)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this stepper runs on one GPU; --gpus must be 1 "
@@ -105,6 +136,8 @@ def main():
     t0 = time.perf_counter()
     spec = beds.metric_bed(args.n, seed=args.seed)
     log(f"bed generated: n={spec.n} side={spec.box[0]:.4f} m in {time.perf_counter() - t0:.1f} s")
+    if args.settle > 0:
+        settle_bed(spec, args.settle)
     bed = Bed(spec, rebuild_every=args.rebuild_every, skin=args.skin, block=args.block)
     log("bed created on the GPU")
     done = 0
@@ -143,7 +176,8 @@ def main():
         "dtype": "f32 law, f64 positions/geometry/reactions",
         "data": "synthetic",
         "config": {"workload": "graded bed, 2M spheres, r0 1.5 mm, L 20 mm, k 1, cap 8 r0, 0.2 m deep, "
-                               "periodic, floor, dt 2e-6 s",
+                               "periodic, floor, dt 2e-6 s, settled",
+                   "settle_steps": args.settle,
                    "n": N, "side_m": spec.box[0], "rebuild_every": args.rebuild_every, "skin_m": args.skin},
         "contacts_per_s": pairs * args.steps / wall,
         "contacts_per_particle": cbar,

@@ -42,7 +42,8 @@ struct DevBufs {
   // records
   float4* frc;           // optional
   float4* trq;
-  double* partial;       // [nblocks(256-thread)][MAXB][6]
+  double* partial;       // [bodies][6][nblk] block partial sums of reactions
+  int64_t nblk;          // blocks of the smallest step-kernel block size (N / 64)
   // scan scratch
   uint32_t* scan_tmp;
   // tables

@@ -286,7 +286,8 @@ __global__ __launch_bounds__(SEARCH_BS) void k_search(DevBufs d, int s, int lo, 
     }
   d.own_cnt[ln][i] = cnt;
   d.cflag[hn][i] = fn;
-  atomicMax(&d.stat[0], (uint32_t)cnt);
+  // largest owner count seen: an atomic only when this count raises it
+  if ((uint32_t)cnt > *(const volatile uint32_t*)&d.stat[0]) atomicMax(&d.stat[0], (uint32_t)cnt);
 }
 
 void launch_search(const DevBufs& d, int s, int lo, int ho, hipStream_t st) {
@@ -481,7 +482,8 @@ __global__ __launch_bounds__(BS) void k_step(DevBufs d, StepPar p, int record) {
         r6[5] += (rx * fy - ry * fx) - (double)out.M.z;
       }
     }
-    double* part = d.partial + ((int64_t)blockIdx.x * MAXB + b) * 6;
+    // partial sums are component-major: [bed body][component][block]
+    double* part = d.partial + (int64_t)(bc.body0 + b) * 6 * d.nblk + blockIdx.x;
     if (__syncthreads_or(hit)) {
       const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
       for (int c = 0; c < 6; ++c) {
@@ -492,11 +494,11 @@ __global__ __launch_bounds__(BS) void k_step(DevBufs d, StepPar p, int record) {
       if (threadIdx.x < 6) {
         double acc = 0.0;
         for (int q = 0; q < BS / 64; ++q) acc += red[q][threadIdx.x];
-        part[threadIdx.x] = acc;
+        part[(int64_t)threadIdx.x * d.nblk] = acc;
       }
       __syncthreads();
     } else if (threadIdx.x < 6) {
-      part[threadIdx.x] = 0.0;
+      part[(int64_t)threadIdx.x * d.nblk] = 0.0;
     }
   }
   if (!active) return;
@@ -577,7 +579,7 @@ LPR_DEV_INLINE void make_pose(const WallDef& W, const BodyDef& B, const BodyDyn&
   P.body = W.body;
 }
 
-constexpr int ADV_BS = 256;
+constexpr int ADV_BS = 1024;
 
 __global__ __launch_bounds__(ADV_BS) void k_advance(DevBufs d, int step_block) {
   __shared__ double red[ADV_BS];
@@ -587,8 +589,9 @@ __global__ __launch_bounds__(ADV_BS) void k_advance(DevBufs d, int step_block) {
   const int64_t blk0 = bc.p0 / step_block, blk1 = bc.p1 / step_block;
   for (int b = 0; b < bc.nbody; ++b) {
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t q = blk0 + threadIdx.x; q < blk1; q += ADV_BS)
-      for (int c = 0; c < 6; ++c) acc[c] += d.partial[(q * MAXB + b) * 6 + c];
+    const double* part = d.partial + (int64_t)(bc.body0 + b) * 6 * d.nblk;
+    for (int c = 0; c < 6; ++c)
+      for (int64_t q = blk0 + threadIdx.x; q < blk1; q += ADV_BS) acc[c] += part[(int64_t)c * d.nblk + q];
     double tot[6];
     for (int c = 0; c < 6; ++c) {
       red[threadIdx.x] = acc[c];

@@ -422,7 +422,8 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   ok &= dal(b, &d.own_rank, (size_t)K * N) && dal(b, &d.rev_cnt, N) && dal(b, &d.rev_start, N + 1);
   ok &= dal(b, &d.rev_ent, (size_t)K * N);
   if (b->record) ok &= dal(b, &d.frc, N) && dal(b, &d.trq, N);
-  ok &= dal(b, &d.partial, (size_t)(N / 64) * MAXB * 6);
+  d.nblk = N / 64;
+  ok &= dal(b, &d.partial, (size_t)d.nblk * 6 * std::max(1, body_total));
   ok &= dal(b, &d.scan_tmp, std::max(scan_tmp_elems(cell_base), scan_tmp_elems(N + 1)));
   ok &= dal(b, &d.beds, nb) && dal(b, &d.levels, levels.size());
   ok &= dal(b, &d.wdefs, std::max(1, wall_total)) && dal(b, &d.walls, std::max(1, wall_total));
@@ -549,7 +550,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   }
   e = (hipError_t)(e | hipMemsetAsync(d.err, 0, sizeof(uint32_t), st));
   e = (hipError_t)(e | hipMemsetAsync(d.stat, 0, sizeof(uint32_t) * 4, st));
-  e = (hipError_t)(e | hipMemsetAsync(d.partial, 0, sizeof(double) * (N / 64) * MAXB * 6, st));
+  e = (hipError_t)(e | hipMemsetAsync(d.partial, 0, sizeof(double) * d.nblk * 6 * std::max(1, body_total), st));
   if (b->record) {
     e = (hipError_t)(e | hipMemsetAsync(d.frc, 0, sizeof(float4) * N, st));
     e = (hipError_t)(e | hipMemsetAsync(d.trq, 0, sizeof(float4) * N, st));
