@@ -120,6 +120,10 @@ def main():
     ap.add_argument("--skin", type=float, default=0.0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--secondary-every", type=int, default=50,
+                    help="also time candidate lists with a skin rebuilt every k steps (0: skip)")
+    ap.add_argument("--secondary-skin", type=float, default=0.05,
+                    help="skin of the secondary run, as a fraction of the smallest radius")
     ap.add_argument("--settle", type=int, default=20000,
                     help="relaxation steps before the measurement (paper's reduced friction, damped, dt 5e-6)")
     args = ap.parse_args()
@@ -188,6 +192,30 @@ def main():
                      "bytes_per_particle_step": b_alg},
         "algorithmic_frac_whole_step": N * b_alg / (wall / args.steps) / 1e9 / HBM_PEAK_GBS,
     }
+    if args.secondary_every > 1:
+        bed.close()
+        skin = args.secondary_skin * float(spec.radius.min())
+        bed = Bed(spec, rebuild_every=args.secondary_every, skin=skin, block=args.block)
+        bed.step(args.warmup)
+        bed.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof2 = bed.step_profiled(args.steps)
+        torch.cuda.synchronize()
+        wall2 = time.perf_counter() - t1
+        st2 = bed.stats()
+        log(f"skin lists (every {args.secondary_every}, skin {skin:.2e} m): {args.steps} steps in {wall2:.3f} s; "
+            f"kernels {prof2}; trips {st2['skin_trips']}")
+        step2 = prof2["step"] / args.steps
+        b2 = B_PARTICLE + B_PAIR * st2["contacts"] / N
+        out["skin_lists"] = {
+            "value": N * args.steps / wall2, "ms_per_step": 1e3 * wall2 / args.steps,
+            "rebuild_every": args.secondary_every, "skin_m": skin, "skin_trips": st2["skin_trips"],
+            "contacts_per_particle": st2["contacts"] / N, "candidates_per_particle": st2["candidates"] / N,
+            "kernel_ms_per_step": {k: v / args.steps for k, v in prof2.items()},
+            "step_kernel_achieved_GBs": N * b2 / (step2 * 1e-3) / 1e9,
+            "step_kernel_frac": N * b2 / (step2 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        }
     if args.cpu_steps > 0:
         pos, vel, omg = bed.state()
         keys, vals = bed.history()

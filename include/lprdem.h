@@ -219,8 +219,9 @@ typedef struct {
   int64_t rebuilds;         /* broad-phase rebuilds performed */
   int32_t levels;           /* cell-list levels */
   int64_t cells;            /* cells over all levels */
-  int32_t max_owner_slots;  /* largest per-owner candidate count seen at
-                               the last rebuild */
+  int32_t max_owner_slots;  /* largest per-owner candidate count seen */
+  int64_t skin_trips;       /* times a skin was exceeded between rebuilds
+                               (those steps were rebuilt and repeated) */
 } lpr_stats;
 lpr_status lpr_get_stats(lpr_bed* bed, lpr_stats* out);
 

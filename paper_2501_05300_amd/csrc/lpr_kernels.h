@@ -46,6 +46,10 @@ struct DevBufs {
   int64_t nblk;          // blocks of the smallest step-kernel block size (N / 64)
   // scan scratch
   uint32_t* scan_tmp;
+  float4* posf;          // FP32 (x, y, z, r) written at each rebuild
+  int32_t* zext;         // [levels][2] occupied z-row range (monotone)
+  float* disp;           // distance bound moved since the last rebuild
+  uint32_t* viol;        // [2] skin-exceeded flags, by state parity
   // tables
   BedConst* beds;
   LevelGrid* levels;

@@ -76,18 +76,33 @@ LPR_DEV_INLINE int axis_neighbours(const LevelGrid& G, int a, int c, int out[3])
 // ---------------------------------------------------------------------------
 // binning
 
+// Cell row of z in a level grid before clamping (bounded to +-2^30).
+LPR_DEV_INLINE int row_unclamped(const LevelGrid& G, double z) {
+#pragma clang fp contract(off)
+  const double f = fmin(fmax((z - G.lo[2]) * G.inv_w[2], -1073741824.0), 1073741824.0);
+  return (int)floor(f);
+}
+
+// Bins every particle into the grid of its own level, writes the compact
+// FP32 copy (x, y, z, r) the search scans, and widens the level's occupied
+// z-row range (monotone, so a stale range is still a superset).
 __global__ void k_bin(DevBufs d, int s) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= d.N || latched(d.err)) return;
   const uint32_t m = d.meta[i];
   if (m == INACTIVE) return;
   const BedConst& bc = d.beds[m >> 8];
-  const LevelGrid& G = d.levels[bc.lev0 + (int)(m & 0xffu)];
+  const int gl = bc.lev0 + (int)(m & 0xffu);
+  const LevelGrid& G = d.levels[gl];
   const double4 p = d.pos[s][i];
   const int cx = cell_axis(G, 0, p.x), cy = cell_axis(G, 1, p.y), cz = cell_axis(G, 2, p.z);
   const int32_t c = (int32_t)(G.base + ((int64_t)cz * G.n[1] + cy) * G.n[0] + cx);
   d.pcell[i] = c;
   d.prank[i] = atomicAdd(&d.cell_cnt[c], 1u);
+  d.posf[i] = make_float4((float)p.x, (float)p.y, (float)p.z, (float)p.w);
+  const int zu = row_unclamped(G, p.z);
+  if (zu < *(const volatile int*)&d.zext[2 * gl]) atomicMin(&d.zext[2 * gl], zu);
+  if (zu > *(const volatile int*)&d.zext[2 * gl + 1]) atomicMax(&d.zext[2 * gl + 1], zu);
 }
 
 void launch_bin(const DevBufs& d, int s, hipStream_t st) {
@@ -201,6 +216,10 @@ __global__ __launch_bounds__(SEARCH_BS) void k_search(DevBufs d, int s, int lo, 
   if (i >= d.N || latched(d.err)) return;
   const int ln = lo ^ 1, hn = ho ^ 1;
   const int64_t N = d.N;
+  if (i == 0) {  // fresh lists: no displacement since they were built
+    d.viol[0] = 0u;
+    d.viol[1] = 0u;
+  }
   const uint32_t m = d.meta[i];
   if (m == INACTIVE) {
     d.own_cnt[ln][i] = 0;
@@ -210,13 +229,24 @@ __global__ __launch_bounds__(SEARCH_BS) void k_search(DevBufs d, int s, int lo, 
   const BedConst& bc = d.beds[m >> 8];
   const int lev_i = (int)(m & 0xffu);
   const double4 pi = d.pos[s][i];
-  const float ri = (float)pi.w;
+  const float4 pf = d.posf[i];
+  const float ri = pf.w;
   const int32_t si = d.sid[i];
   const double skin = (double)bc.skin;
+  const float Lx = (float)bc.L[0], Ly = (float)bc.L[1];
+  const bool perx = (bc.periodic & 1u) != 0, pery = (bc.periodic & 2u) != 0;
+  const float reach = ri + bc.skin + bc.bp_tol;
   int cnt = 0;
   bool ovf = false;
   for (int lev = lev_i; lev < bc.nlev; ++lev) {
     const LevelGrid& G = d.levels[bc.lev0 + lev];
+    if (lev > lev_i) {
+      // a coarser level whose particles all sit more than one row away
+      // cannot touch this particle
+      const int zu = row_unclamped(G, pi.z);
+      const int gl = bc.lev0 + lev;
+      if (zu < d.zext[2 * gl] - 1 || zu > d.zext[2 * gl + 1] + 1) continue;
+    }
     int lx[3], ly[3], lz[3];
     const int nxl = axis_neighbours(G, 0, cell_axis(G, 0, pi.x), lx);
     const int nyl = axis_neighbours(G, 1, cell_axis(G, 1, pi.y), ly);
@@ -228,9 +258,19 @@ __global__ __launch_bounds__(SEARCH_BS) void k_search(DevBufs d, int s, int lo, 
           const uint32_t c0 = d.cell_start[c], c1 = d.cell_start[c + 1];
           for (uint32_t q = c0; q < c1; ++q) {
             const int32_t j = d.cell_list[q];
-            const double4 pj = d.pos[s][j];
+            // conservative FP32 pre-test on the compact copy; the FP64
+            // predicate below decides
+            const float4 qf = d.posf[j];
+            if (qf.w < ri) continue;  // j owns the pair
+            float fx = qf.x - pf.x, fy = qf.y - pf.y;
+            const float fz = qf.z - pf.z;
+            if (perx) fx = (fx > 0.5f * Lx) ? fx - Lx : ((fx < -0.5f * Lx) ? fx + Lx : fx);
+            if (pery) fy = (fy > 0.5f * Ly) ? fy - Ly : ((fy < -0.5f * Ly) ? fy + Ly : fy);
+            const float Rf = reach + qf.w;
+            if (fx * fx + fy * fy + fz * fz >= Rf * Rf) continue;
             const int32_t sj = d.sid[j];
-            if (!owner_rule(ri, si, (float)pj.w, sj)) continue;
+            if (qf.w == ri && sj <= si) continue;  // equal radii: smaller id owns
+            const double4 pj = d.pos[s][j];
             double dx, dy, dz;
             const double d2 = pair_sep(bc, pi, pj, dx, dy, dz);
             if (within_skin(d2, pi.w, pj.w, skin)) {
@@ -286,6 +326,7 @@ __global__ __launch_bounds__(SEARCH_BS) void k_search(DevBufs d, int s, int lo, 
     }
   d.own_cnt[ln][i] = cnt;
   d.cflag[hn][i] = fn;
+  d.disp[i] = 0.f;
   // largest owner count seen: an atomic only when this count raises it
   if ((uint32_t)cnt > *(const volatile uint32_t*)&d.stat[0]) atomicMax(&d.stat[0], (uint32_t)cnt);
 }
@@ -344,6 +385,17 @@ __global__ __launch_bounds__(BS) void k_step(DevBufs d, StepPar p, int record) {
   const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   const int bed = d.chunk_bed32[(blockIdx.x * (int64_t)BS) >> 8];
   const BedConst bc = d.beds[bed];
+  if (bc.skin > 0.f) {
+    // candidate lists with a skin are complete only while every particle
+    // has moved less than skin/2 since they were built; otherwise stop
+    // before using them (the host rebuilds and repeats the step).  The flag
+    // read here was raised by the previous step (flags alternate with the
+    // state parity, so this step's own raises go to the other flag).
+    if (*(const volatile uint32_t*)&d.viol[p.s] != 0u) {
+      if (threadIdx.x == 0) atomicOr(d.err, ERR_SKIN);
+      return;
+    }
+  }
   const uint32_t m = d.meta[i];
   const bool active = (m != INACTIVE);
   const int s = p.s, sn = p.s ^ 1, h = p.h, hn = p.h ^ 1, l = p.l;
@@ -528,6 +580,12 @@ __global__ __launch_bounds__(BS) void k_step(DevBufs d, StepPar p, int record) {
   if (!(isfinite(vx) && isfinite(vy) && isfinite(vz) && isfinite(ox) && isfinite(oy) && isfinite(oz) &&
         isfinite(x) && isfinite(y) && isfinite(z)))
     atomicOr(d.err, ERR_NUMERIC);
+  if (bc.skin > 0.f) {
+    // bound on the distance moved since the lists were built: |dx| = dt |v|
+    const float moved = d.disp[i] + bc.dt * sqrtf(vx * vx + vy * vy + vz * vz);
+    d.disp[i] = moved;
+    if (moved > 0.45f * bc.skin) atomicOr(&d.viol[sn], 1u);
+  }
   d.pos[sn][i] = make_double4(x, y, z, xi.w);
   d.vel[sn][i] = make_float4(vx, vy, vz, vi.w);
   d.omg[sn][i] = make_float4(ox, oy, oz, wi.w);

@@ -80,6 +80,13 @@ bool finite_arrf(const float* a, int64_t n) {
 
 }  // namespace
 
+// Host view of the buffer parities (state, history, lists) and the steps
+// since the last broad-phase rebuild.
+struct Par {
+  int s = 0, h = 0, l = 0;
+  int64_t since = std::numeric_limits<int64_t>::max() / 2;
+};
+
 struct lpr_bed {
   lpr_allocator alloc{};
   bool use_hip_malloc = true;
@@ -97,6 +104,11 @@ struct lpr_bed {
   int64_t since = std::numeric_limits<int64_t>::max() / 2;  // steps since the last rebuild
   int64_t host_steps = 0;
   int64_t rebuilds = 0;
+  // parity log since the last clean sync, for rewinding after a skin trip
+  int64_t base_steps = 0;
+  Par base_par;
+  std::vector<Par> plog;
+  int64_t skin_trips = 0;
   // captured cycle
   bool has_graph = false;
   hipGraph_t graph = nullptr;
@@ -257,11 +269,67 @@ void plan_bed(const lpr_bed_desc* D, double band_ratio, double cell_factor, doub
   for (int64_t i = 0; i < n; ++i) H.inv[H.perm[i]] = i;
 }
 
+Par cur_par(const lpr_bed* b) {
+  Par p;
+  p.s = b->s; p.h = b->h; p.l = b->l; p.since = b->since;
+  return p;
+}
+
+void set_par(lpr_bed* b, const Par& p) {
+  b->s = p.s; b->h = p.h; b->l = p.l; b->since = p.since;
+}
+
+// Parity changes of one step, as enqueue_step makes them.
+void simulate_step(Par& p, int R) {
+  if (p.since >= R) {
+    p.l ^= 1;
+    p.h ^= 1;
+    p.since = 0;
+  }
+  p.s ^= 1;
+  p.h ^= 1;
+  p.since += 1;
+}
+
+void enqueue_step(lpr_bed* b);
+
 lpr_status sync_check(lpr_bed* b) {
-  HIPTRY(hipStreamSynchronize(b->stream));
+  for (;;) {
+    HIPTRY(hipStreamSynchronize(b->stream));
+    uint32_t e = 0;
+    HIPTRY(hipMemcpy(&e, b->d.err, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (e == 0) {
+      b->base_steps = b->host_steps;
+      b->base_par = cur_par(b);
+      b->plog.clear();
+      return LPR_OK;
+    }
+    if (e != ERR_SKIN) break;
+    // A particle moved more than skin/2 since the candidate lists were
+    // built: the steps from there on were skipped whole.  Rewind the host
+    // view to the last completed step, rebuild, and run the rest again.
+    BedDyn bd;
+    HIPTRY(hipMemcpy(&bd, b->d.bedyn, sizeof(BedDyn), hipMemcpyDeviceToHost));
+    const int64_t done = bd.completed - b->base_steps;
+    if (done < 0 || done > (int64_t)b->plog.size()) break;
+    const Par p = (done == 0) ? b->base_par : b->plog[(size_t)(done - 1)];
+    const int64_t remaining = b->host_steps - bd.completed;
+    const uint32_t zero[2] = {0u, 0u};
+    HIPTRY(hipMemcpy(b->d.err, zero, sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(b->d.viol, zero, 2 * sizeof(uint32_t), hipMemcpyHostToDevice));
+    set_par(b, p);
+    b->since = std::numeric_limits<int64_t>::max() / 2;
+    b->host_steps = bd.completed;
+    b->base_steps = bd.completed;
+    b->base_par = cur_par(b);
+    b->plog.clear();
+    b->skin_trips += 1;
+    for (int64_t q = 0; q < remaining; ++q) enqueue_step(b);
+    HIPTRY(hipGetLastError());
+  }
   uint32_t e = 0;
   HIPTRY(hipMemcpy(&e, b->d.err, sizeof(uint32_t), hipMemcpyDeviceToHost));
-  if (e) {
+  {
     b->faulted = true;
     if (e & ERR_CAPACITY) b->fault_status = LPR_E_CAPACITY;
     else if (e & ERR_NUMERIC) b->fault_status = LPR_E_NUMERIC;
@@ -299,12 +367,14 @@ void enqueue_step(lpr_bed* b) {
   b->h ^= 1;
   b->since += 1;
   b->host_steps += 1;
+  b->plog.push_back(cur_par(b));
 }
 
 lpr_status capture_cycle(lpr_bed* b) {
   const int S = 2 * b->R;
   const int s0 = b->s, h0 = b->h, l0 = b->l;
   const int64_t since0 = b->since, steps0 = b->host_steps, reb0 = b->rebuilds;
+  const size_t plog0 = b->plog.size();
   HIPTRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
   for (int q = 0; q < S; ++q) enqueue_step(b);
   hipGraph_t g = nullptr;
@@ -319,6 +389,7 @@ lpr_status capture_cycle(lpr_bed* b) {
   // the capture only recorded; restore the host view
   b->s = s0; b->h = h0; b->l = l0;
   b->since = since0; b->host_steps = steps0; b->rebuilds = reb0;
+  b->plog.resize(plog0);
   return LPR_OK;
 }
 
@@ -336,6 +407,10 @@ lpr_status ensure_lists(lpr_bed* b) {
 // Parity of the buffers holding the state after the completed steps.
 lpr_status state_parity(lpr_bed* b, int* par) {
   BedDyn bd;
+  if (!b->faulted) {
+    lpr_status st = sync_check(b);
+    if (st != LPR_OK && st != LPR_E_CAPACITY && st != LPR_E_NUMERIC) return st;
+  }
   HIPTRY(hipStreamSynchronize(b->stream));
   HIPTRY(hipMemcpy(&bd, b->d.bedyn, sizeof(BedDyn), hipMemcpyDeviceToHost));
   *par = (int)(bd.completed & 1);
@@ -419,6 +494,8 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   ok &= dal(b, &d.sid, N) && dal(b, &d.meta, N) && dal(b, &d.chunk_bed32, N / PAD);
   ok &= dal(b, &d.cell_cnt, cell_base) && dal(b, &d.cell_start, cell_base + 1);
   ok &= dal(b, &d.pcell, N) && dal(b, &d.prank, N) && dal(b, &d.cell_list, N);
+  ok &= dal(b, &d.posf, N) && dal(b, &d.zext, 2 * levels.size());
+  ok &= dal(b, &d.disp, N) && dal(b, &d.viol, 2);
   ok &= dal(b, &d.own_rank, (size_t)K * N) && dal(b, &d.rev_cnt, N) && dal(b, &d.rev_start, N + 1);
   ok &= dal(b, &d.rev_ent, (size_t)K * N);
   if (b->record) ok &= dal(b, &d.frc, N) && dal(b, &d.trq, N);
@@ -478,6 +555,12 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
     C.p0 = (int32_t)H.p0;
     C.p1 = (int32_t)(H.p0 + H.npad);
     C.skin = b->skin;
+    {
+      // margin of the FP32 pre-test: 32 ulp of the largest coordinate
+      double mc = std::max(std::fabs(D->box[0]), std::fabs(D->box[1]));
+      for (int64_t i = 0; i < 3 * D->n; ++i) mc = std::max(mc, std::fabs(D->pos[i]));
+      C.bp_tol = (float)(32.0 * std::ldexp(1.0, std::ilogb(std::max(mc, 1e-3)) - 23));
+    }
     const double Estar = 1.0 / ((1.0 - P.nu * P.nu) / P.E + (1.0 - P.nu * P.nu) / P.E);
     C.kfac = (float)(P.s_k * Estar / 3.0);
     C.gn = (float)(P.gamma_factor * P.dt);
@@ -550,6 +633,14 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   }
   e = (hipError_t)(e | hipMemsetAsync(d.err, 0, sizeof(uint32_t), st));
   e = (hipError_t)(e | hipMemsetAsync(d.stat, 0, sizeof(uint32_t) * 4, st));
+  e = (hipError_t)(e | hipMemsetAsync(d.disp, 0, sizeof(float) * N, st));
+  e = (hipError_t)(e | hipMemsetAsync(d.viol, 0, sizeof(uint32_t) * 2, st));
+  std::vector<int32_t> hz(2 * levels.size());
+  for (size_t q = 0; q < levels.size(); ++q) {
+    hz[2 * q] = std::numeric_limits<int32_t>::max();
+    hz[2 * q + 1] = std::numeric_limits<int32_t>::min();
+  }
+  e = (hipError_t)(e | up(d.zext, hz.data(), sizeof(int32_t) * hz.size()));
   e = (hipError_t)(e | hipMemsetAsync(d.partial, 0, sizeof(double) * d.nblk * 6 * std::max(1, body_total), st));
   if (b->record) {
     e = (hipError_t)(e | hipMemsetAsync(d.frc, 0, sizeof(float4) * N, st));
@@ -615,6 +706,11 @@ lpr_status lpr_step(lpr_bed* b, int64_t n_steps) {
       if (b->s == b->gs && b->h == b->gh && b->l == b->gl) {
         HIPTRY(hipGraphLaunch(b->gexec, b->stream));
         // a cycle flips s twice, h 2R+2 times, l twice: parities unchanged
+        Par p = cur_par(b);
+        for (int q = 0; q < b->gsteps; ++q) {
+          simulate_step(p, b->R);
+          b->plog.push_back(p);
+        }
         b->since = b->R;
         b->host_steps += b->gsteps;
         b->rebuilds += 2;
@@ -650,6 +746,7 @@ lpr_status lpr_step_profiled(lpr_bed* b, int64_t n_steps, double out[4]) {
     b->h ^= 1;
     b->since += 1;
     b->host_steps += 1;
+    b->plog.push_back(cur_par(b));
   }
   HIPTRY(hipGetLastError());
   HIPTRY(hipStreamSynchronize(b->stream));
@@ -978,6 +1075,7 @@ lpr_status lpr_get_stats(lpr_bed* b, lpr_stats* out) {
   out->levels = b->nlev_total;
   out->cells = b->ncells;
   out->max_owner_slots = (int32_t)stat[0];
+  out->skin_trips = b->skin_trips;
   return LPR_OK;
 }
 

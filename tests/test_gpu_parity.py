@@ -155,3 +155,27 @@ def test_plate_reaction_parity():
     R = bed.reaction(1)
     assert abs(R[2]) > 0
     assert res["reaction1_rel"] < FTOL
+
+
+@pytest.mark.parametrize("skin,every", [(2e-4, 10), (1e-9, 7)])
+def test_skin_lists_step_bitwise_like_every_step_search(skin, every):
+    """Candidate lists with a skin, rebuilt every few steps, find the same
+    contacts in the same order as a search every step, so the trajectories
+    are bitwise equal; a skin too small to hold forces rebuilds (trips) and
+    still gives the same result."""
+    spec = beds.add_plate(beds.two_layer_bed(4), diameter=0.04, speed=0.5)
+    a = gpu_bed(spec)
+    b = gpu_bed(spec, rebuild_every=every, skin=skin)
+    a.step(150)
+    b.step(150)
+    xa, va, wa = a.state()
+    xb, vb, wb = b.state()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb) and np.array_equal(wa, wb)
+    assert np.array_equal(a.contacts(), b.contacts())
+    np.testing.assert_array_equal(a.reaction(1), b.reaction(1))
+    st = b.stats()
+    print(st)
+    if skin < 1e-6:
+        assert st["skin_trips"] > 0
+    else:
+        assert st["rebuilds"] < 150
