@@ -62,7 +62,7 @@ def counter_traffic(n_particles):
     return c.get("hbm_bytes_per_launch")
 
 
-def settle_bed(spec, steps, chunk=2000):
+def settle_bed(spec, steps, chunk=5000):
     """Relaxes the deposited bed in place (positions only) with the paper's
     relaxation friction (mu_t 0.1, mu_r 0.01, frictionless walls), extra
     normal damping (gamma_n = 50 dt) and dt = 5e-6 s; velocities are then
@@ -74,7 +74,7 @@ def settle_bed(spec, steps, chunk=2000):
     s.params = beds.settle_params(spec.params).replace(dt=5e-6, gamma_factor=50.0)
     for w in s.walls:
         w.mu_t, w.mu_r = 0.0, 0.0
-    sb = Bed(s, rebuild_every=1)
+    sb = Bed(s, rebuild_every=10, skin=0.1 * float(spec.radius.min()))
     done = 0
     t0 = time.perf_counter()
     while done < steps:
@@ -83,7 +83,8 @@ def settle_bed(spec, steps, chunk=2000):
         sb.sync()
         done += k
         st = sb.stats()
-        log(f"settle {done}/{steps}: contacts/particle {st['contacts'] / spec.n:.3f} ({time.perf_counter() - t0:.1f} s)")
+        log(f"settle {done}/{steps}: contacts/particle {st['contacts'] / spec.n:.3f}, "
+            f"skin trips {st['skin_trips']} ({time.perf_counter() - t0:.1f} s)")
     pos, _, _ = sb.state()
     sb.close()
     spec.pos = pos
@@ -124,7 +125,7 @@ def main():
                     help="also time candidate lists with a skin rebuilt every k steps (0: skip)")
     ap.add_argument("--secondary-skin", type=float, default=0.05,
                     help="skin of the secondary run, as a fraction of the smallest radius")
-    ap.add_argument("--settle", type=int, default=20000,
+    ap.add_argument("--settle", type=int, default=40000,
                     help="relaxation steps before the measurement (paper's reduced friction, damped, dt 5e-6)")
     args = ap.parse_args()
     if args.gpus != 1:
