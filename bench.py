@@ -62,34 +62,90 @@ def counter_traffic(n_particles):
     return c.get("hbm_bytes_per_launch")
 
 
-def settle_bed(spec, steps, chunk=5000):
-    """Relaxes the deposited bed in place (positions only) with the paper's
-    relaxation friction (mu_t 0.1, mu_r 0.01, frictionless walls), extra
-    normal damping (gamma_n = 50 dt) and dt = 5e-6 s; velocities are then
-    zeroed.  Untimed preparation of the input."""
+def settle_beds(specs, steps, chunk=5000):
+    """Relaxes deposited beds in place (positions only), all in one batch,
+    with the paper's relaxation friction (mu_t 0.1, mu_r 0.01, frictionless
+    walls), extra normal damping (gamma_n = 50 dt) and dt = 5e-6 s;
+    velocities are then zeroed.  Untimed preparation of the input."""
     import numpy as np
     from paper_2501_05300_amd import beds
-    from paper_2501_05300_amd.lprdem import Bed
-    s = spec.copy()
-    s.params = beds.settle_params(spec.params).replace(dt=5e-6, gamma_factor=50.0)
-    for w in s.walls:
-        w.mu_t, w.mu_r = 0.0, 0.0
-    sb = Bed(s, rebuild_every=10, skin=0.1 * float(spec.radius.min()))
+    from paper_2501_05300_amd.lprdem import Batch
+    work = []
+    for spec in specs:
+        s = spec.copy()
+        s.params = beds.settle_params(spec.params).replace(dt=5e-6, gamma_factor=50.0)
+        for w in s.walls:
+            w.mu_t, w.mu_r = 0.0, 0.0
+        work.append(s)
+    rmin = min(float(s.radius.min()) for s in specs)
+    sb = Batch(work, rebuild_every=10, skin=0.1 * rmin)
     done = 0
     t0 = time.perf_counter()
+    ntot = sum(s.n for s in specs)
     while done < steps:
         k = min(chunk, steps - done)
         sb.step(k)
         sb.sync()
         done += k
         st = sb.stats()
-        log(f"settle {done}/{steps}: contacts/particle {st['contacts'] / spec.n:.3f}, "
+        log(f"settle {done}/{steps}: contacts/particle {st['contacts'] / ntot:.3f}, "
             f"skin trips {st['skin_trips']} ({time.perf_counter() - t0:.1f} s)")
-    pos, _, _ = sb.state()
+    for q, spec in enumerate(specs):
+        pos, _, _ = sb.state(bed=q)
+        spec.pos = pos
+        spec.vel = np.zeros_like(spec.vel)
+        spec.omega = np.zeros_like(spec.omega)
     sb.close()
-    spec.pos = pos
-    spec.vel = np.zeros_like(spec.vel)
-    spec.omega = np.zeros_like(spec.omega)
+
+
+def batch_leg(steps, warmup, settle, tune_steps):
+    """The 36-bed family in one batch vs the same beds stepped one at a time
+    with the plain stepper, plus the autotuned batch."""
+    import torch
+    from paper_2501_05300_amd import beds
+    from paper_2501_05300_amd.lprdem import Batch, Bed, autotune
+    specs = beds.batch_family(plate=False)
+    N = sum(s.n for s in specs)
+    log(f"batch family: {len(specs)} beds, {N} spheres")
+    if settle > 0:
+        settle_beds(specs, settle)
+    specs = [beds.add_plate(s, diameter=0.1, speed=0.01) for s in specs]
+
+    def timed(stepper):
+        stepper.step(warmup)
+        stepper.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stepper.step(steps)
+        stepper.sync()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    b = Batch(specs)
+    wall_b = timed(b)
+    st = b.stats()
+    b.close()
+    log(f"batched: {steps} steps in {wall_b:.3f} s")
+    best, trials = autotune(specs, trial_steps=tune_steps)
+    log(f"autotuner: {best}")
+    tb = Batch(specs, band_ratio=best["band_ratio"], cell_factor=best["cell_factor"], block=best["block"],
+               persistent=best["persistent"])
+    wall_t = timed(tb)
+    tb.close()
+    log(f"batched, tuned: {steps} steps in {wall_t:.3f} s")
+    wall_s = 0.0
+    for s in specs:
+        one = Bed(s)
+        wall_s += timed(one)
+        one.close()
+    log(f"one bed at a time: {steps} steps each in {wall_s:.3f} s total")
+    return {"beds": len(specs), "spheres": N, "steps": steps,
+            "batched_particle_steps_per_s": N * steps / wall_b,
+            "batched_tuned_particle_steps_per_s": N * steps / wall_t,
+            "sequential_plain_particle_steps_per_s": N * steps / wall_s,
+            "speedup_batched_vs_plain": wall_s / wall_b, "speedup_tuned_vs_plain": wall_s / wall_t,
+            "contacts_per_particle": st["contacts"] / N, "tuning": best, "tuning_trials": trials,
+            "graph": "steady cycle replayed as one captured HIP graph"}
 
 
 def cpu_baseline(spec, pos, vel, omg, keys, vals, clock, steps):
@@ -125,6 +181,8 @@ def main():
                     help="also time candidate lists with a skin rebuilt every k steps (0: skip)")
     ap.add_argument("--secondary-skin", type=float, default=0.05,
                     help="skin of the secondary run, as a fraction of the smallest radius")
+    ap.add_argument("--batch-steps", type=int, default=300, help="timed steps of the 36-bed leg (0: skip)")
+    ap.add_argument("--batch-settle", type=int, default=10000)
     ap.add_argument("--settle", type=int, default=40000,
                     help="relaxation steps before the measurement (paper's reduced friction, damped, dt 5e-6)")
     args = ap.parse_args()
@@ -142,7 +200,7 @@ def main():
     spec = beds.metric_bed(args.n, seed=args.seed)
     log(f"bed generated: n={spec.n} side={spec.box[0]:.4f} m in {time.perf_counter() - t0:.1f} s")
     if args.settle > 0:
-        settle_bed(spec, args.settle)
+        settle_beds([spec], args.settle)
     bed = Bed(spec, rebuild_every=args.rebuild_every, skin=args.skin, block=args.block)
     log("bed created on the GPU")
     done = 0
@@ -225,6 +283,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(spec, pos, vel.astype(np.float64), omg.astype(np.float64), keys,
                                            vals.astype(np.float64), clock, args.cpu_steps)
     bed.close()
+    if args.batch_steps > 0:
+        out["batched"] = batch_leg(args.batch_steps, 100, args.batch_settle, 10)
     print(json.dumps(out), flush=True)
 
 

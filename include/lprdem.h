@@ -135,6 +135,8 @@ typedef struct {
                               or 256 (0: 256) */
   int32_t record_forces;   /* 1: keep the last step's per-particle contact
                               forces and torques for lpr_read_forces */
+  int32_t persistent;      /* 1: the step kernel runs as one persistent grid
+                              that fills the GPU (same results) */
 } lpr_bed_desc;
 
 #define LPR_MAX_WALLS 16
@@ -224,6 +226,57 @@ typedef struct {
                                (those steps were rebuilt and repeated) */
 } lpr_stats;
 lpr_status lpr_get_stats(lpr_bed* bed, lpr_stats* out);
+
+/* ---- batched beds ----------------------------------------------------
+ * Many beds (uneven sizes and grading) stepped together: every kernel of a
+ * step covers all beds in one launch, and the steady cycle is one captured
+ * HIP graph.  Beds are independent (no contacts across beds); each keeps its
+ * own parameters, walls, bodies, clock and cell-list layout (band_ratio,
+ * cell_factor).  rebuild_every, skin, block, persistent and record_forces
+ * must agree across the descriptions.  lpr_step, lpr_step_profiled,
+ * lpr_sync, lpr_get_stats and lpr_bed_destroy take the batch handle; the
+ * per-bed reads below take a bed index (the single-bed functions address
+ * bed 0). */
+lpr_status lpr_batch_create(const lpr_bed_desc* const* descs, int32_t n_beds, const lpr_allocator* alloc,
+                            void* hip_stream, lpr_bed** out);
+lpr_status lpr_batch_size(lpr_bed* batch, int32_t* n_beds);
+lpr_status lpr_batch_get_state(lpr_bed* batch, int32_t bed, double* pos, float* vel, float* omega);
+lpr_status lpr_batch_set_state(lpr_bed* batch, int32_t bed, const double* pos, const float* vel,
+                               const float* omega);
+lpr_status lpr_batch_get_history(lpr_bed* batch, int32_t bed, lpr_history* out, int64_t capacity,
+                                 int64_t* n_total);
+lpr_status lpr_batch_set_history(lpr_bed* batch, int32_t bed, const lpr_history* rec, int64_t count);
+lpr_status lpr_batch_read_contacts(lpr_bed* batch, int32_t bed, lpr_contact* out, int64_t capacity,
+                                   int64_t* n_total);
+lpr_status lpr_batch_read_forces(lpr_bed* batch, int32_t bed, float* force, float* torque);
+lpr_status lpr_batch_read_reaction(lpr_bed* batch, int32_t bed, int32_t body, double out6[6]);
+lpr_status lpr_batch_reaction_window(lpr_bed* batch, int32_t bed, int32_t body, double sum6[6], int64_t* steps,
+                                     int32_t reset);
+lpr_status lpr_batch_read_body(lpr_bed* batch, int32_t bed, int32_t body, double origin[3], double vel[3]);
+lpr_status lpr_batch_set_clock(lpr_bed* batch, int32_t bed, int64_t step);
+lpr_status lpr_batch_get_clock(lpr_bed* batch, int32_t bed, int64_t* step);
+lpr_status lpr_batch_set_body_state(lpr_bed* batch, int32_t bed, int32_t body, double z, double vz);
+
+/* Changes the step kernel's launch shape (64/128/256 threads, persistent
+ * grid or not) of a bed or batch; results are unchanged. */
+lpr_status lpr_set_launch(lpr_bed* bed, int32_t block, int32_t persistent);
+
+/* Autotuner.  Times `trial_steps` steps of throwaway copies of the beds
+ * for each cell-list layout (band_ratio in {1.5, 2, 3} x cell_factor in
+ * {1, 1.25}), then each launch shape (block 64/128/256, persistent or not)
+ * on the fastest layout, and returns the fastest setting in *best (and
+ * every trial in `trials`, up to `capacity`; *n_trials gets the count).
+ * None of these choices changes the contacts found or the results. */
+typedef struct {
+  float band_ratio;
+  float cell_factor;
+  int32_t block;
+  int32_t persistent;
+  double ms_per_step;
+} lpr_tuning;
+lpr_status lpr_autotune(const lpr_bed_desc* const* descs, int32_t n_beds, const lpr_allocator* alloc,
+                        void* hip_stream, int32_t trial_steps, lpr_tuning* best, lpr_tuning* trials,
+                        int32_t capacity, int32_t* n_trials);
 
 const char* lpr_status_str(lpr_status s);
 /* Message of the last error on the calling thread ("" if none). */

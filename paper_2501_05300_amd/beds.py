@@ -463,3 +463,27 @@ def metric_bed(n=2_000_000, seed=0) -> BedSpec:
     """The throughput workload: 2M spheres, r0 1.5 mm, L 20 mm, k = 1, cap
     8 r0, 0.2 m deep, periodic side from the count model, floor."""
     return graded_bed(n, r0=1.5e-3, L=0.02, k=1.0, cap=8.0, depth=0.2, seed=seed)
+
+
+def batch_family(seed=0, depth=0.2, side=0.435, min_count=20_000, cap=8.0, plate=True):
+    """The 36-bed family: full factorial r0 in {1.5, 2, 3} mm x L in {10, 20,
+    40} mm x k in {0.5, 1, 1.5, 2}, depth 0.2 m, cap 8 r0, common periodic
+    side 0.435 m; beds that would hold fewer than 20k spheres are widened to
+    20k.  Each bed gets its own 0.1 m plate pushed at 0.01 m/s."""
+    specs = []
+    q = 0
+    for r0 in (1.5e-3, 2.0e-3, 3.0e-3):
+        for L in (0.01, 0.02, 0.04):
+            for k in (0.5, 1.0, 1.5, 2.0):
+                prof = graded_profile(r0, L, k, cap)
+                n = int(round(side * side * count_per_area(prof, depth)))
+                s = side
+                if n < min_count:
+                    n = min_count
+                    s = side_for_count(n, prof, depth)
+                spec = graded_bed(n, r0=r0, L=L, k=k, cap=cap, depth=depth, side=s, seed=seed * 1000 + q)
+                if plate:
+                    spec = add_plate(spec, diameter=0.1, speed=0.01)
+                specs.append(spec)
+                q += 1
+    return specs

@@ -79,7 +79,9 @@ void launch_scatter(const DevBufs& d, hipStream_t st);
 void launch_search(const DevBufs& d, int s, int l_old, int h_old, hipStream_t st);
 void launch_rev_scatter(const DevBufs& d, int l, hipStream_t st);
 void launch_rev_sort(const DevBufs& d, hipStream_t st);
-void launch_step(const DevBufs& d, const StepPar& p, int block, int record, hipStream_t st);
+// persist_blocks > 0: persistent grid of that many launch blocks.
+void launch_step(const DevBufs& d, const StepPar& p, int block, int record, int persist_blocks, hipStream_t st);
+int step_occupancy(int block);
 void launch_advance(const DevBufs& d, int block, hipStream_t st);
 void launch_poses(const DevBufs& d, hipStream_t st);
 size_t scan_tmp_elems(int64_t n);

@@ -377,13 +377,24 @@ LPR_DEV_INLINE double wave_sum(double v) {
   return v;
 }
 
+// Work block handled by launch block b of a grid of g blocks: the blocks
+// that the hardware places on one XCD (b mod 8) take one contiguous range of
+// particles, so neighbours they gather share that XCD's L2.
+LPR_DEV_INLINE int64_t xcd_block(int64_t b, int64_t g) {
+  const int64_t chunk = (g + 7) / 8;
+  const int64_t x = b & 7, q = b >> 3;
+  const int64_t w = x * chunk + q;
+  return w < g ? w : -1;
+}
+
+// One work block of the fused step (all threads of the launch block).
 template <int BS>
-__global__ __launch_bounds__(BS) void k_step(DevBufs d, StepPar p, int record) {
+__device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, int record, int64_t blk) {
   __shared__ double red[BS / 64][6];
   if (__syncthreads_or(latched(d.err) ? 1 : 0)) return;  // uniform per block
   const int64_t N = d.N;
-  const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
-  const int bed = d.chunk_bed32[(blockIdx.x * (int64_t)BS) >> 8];
+  const int64_t i = blk * BS + threadIdx.x;
+  const int bed = d.chunk_bed32[(blk * BS) >> 8];
   const BedConst bc = d.beds[bed];
   if (bc.skin > 0.f) {
     // candidate lists with a skin are complete only while every particle
@@ -535,7 +546,7 @@ __global__ __launch_bounds__(BS) void k_step(DevBufs d, StepPar p, int record) {
       }
     }
     // partial sums are component-major: [bed body][component][block]
-    double* part = d.partial + (int64_t)(bc.body0 + b) * 6 * d.nblk + blockIdx.x;
+    double* part = d.partial + (int64_t)(bc.body0 + b) * 6 * d.nblk + blk;
     if (__syncthreads_or(hit)) {
       const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
       for (int c = 0; c < 6; ++c) {
@@ -591,13 +602,52 @@ __global__ __launch_bounds__(BS) void k_step(DevBufs d, StepPar p, int record) {
   d.omg[sn][i] = make_float4(ox, oy, oz, wi.w);
 }
 
-void launch_step(const DevBufs& d, const StepPar& p, int block, int record, hipStream_t st) {
-  if (block == 64)
-    hipLaunchKernelGGL(k_step<64>, dim3((unsigned)(d.N / 64)), dim3(64), 0, st, d, p, record);
-  else if (block == 128)
-    hipLaunchKernelGGL(k_step<128>, dim3((unsigned)(d.N / 128)), dim3(128), 0, st, d, p, record);
-  else
-    hipLaunchKernelGGL(k_step<256>, dim3((unsigned)(d.N / 256)), dim3(256), 0, st, d, p, record);
+// One launch block per work block, XCD-aware placement.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_step(DevBufs d, StepPar p, int record) {
+  const int64_t g = d.N / BS;
+  const int64_t blk = xcd_block(blockIdx.x, g);
+  if (blk < 0) return;  // whole launch block idle (grid rounded up to 8)
+  step_block<BS>(d, p, record, blk);
+}
+
+// Persistent form: a grid that fills the GPU once; each launch block walks
+// the work blocks of its XCD's contiguous range with a fixed stride, so the
+// assignment (and every result) is deterministic.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_step_persist(DevBufs d, StepPar p, int record) {
+  const int64_t g = d.N / BS;
+  const int64_t chunk = (g + 7) / 8;
+  const int64_t x = blockIdx.x & 7, lanes = gridDim.x >> 3;  // launch blocks per XCD
+  const int64_t end = (x + 1) * chunk < g ? (x + 1) * chunk : g;
+  for (int64_t blk = x * chunk + (blockIdx.x >> 3); blk < end; blk += lanes) step_block<BS>(d, p, record, blk);
+}
+
+template <int BS>
+void launch_step_t(const DevBufs& d, const StepPar& p, int record, int persist_blocks, hipStream_t st) {
+  const int64_t g = d.N / BS;
+  if (persist_blocks > 0) {
+    const int64_t grid = ((int64_t)persist_blocks + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_step_persist<BS>, dim3((unsigned)grid), dim3(BS), 0, st, d, p, record);
+  } else {
+    const int64_t grid = (g + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_step<BS>, dim3((unsigned)grid), dim3(BS), 0, st, d, p, record);
+  }
+}
+
+void launch_step(const DevBufs& d, const StepPar& p, int block, int record, int persist_blocks, hipStream_t st) {
+  if (block == 64) launch_step_t<64>(d, p, record, persist_blocks, st);
+  else if (block == 128) launch_step_t<128>(d, p, record, persist_blocks, st);
+  else launch_step_t<256>(d, p, record, persist_blocks, st);
+}
+
+int step_occupancy(int block) {
+  int n = 0;
+  hipError_t e;
+  if (block == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_persist<64>, 64, 0);
+  else if (block == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_persist<128>, 128, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_persist<256>, 256, 0);
+  return e == hipSuccess ? n : 0;
 }
 
 // ---------------------------------------------------------------------------

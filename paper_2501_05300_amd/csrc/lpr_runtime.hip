@@ -96,6 +96,7 @@ struct lpr_bed {
   DevBufs d{};
   std::vector<HostBed> hb;
   int block = 256;
+  int persist_blocks = 0;  // > 0: persistent step kernel with this grid
   int record = 0;
   int R = 1;
   float skin = 0.f;
@@ -361,7 +362,7 @@ void enqueue_rebuild(lpr_bed* b) {
 void enqueue_step(lpr_bed* b) {
   if (b->since >= b->R) enqueue_rebuild(b);
   StepPar p{b->s, b->h, b->l, false};
-  launch_step(b->d, p, b->block, b->record, b->stream);
+  launch_step(b->d, p, b->block, b->record, b->persist_blocks, b->stream);
   launch_advance(b->d, b->block, b->stream);
   b->s ^= 1;
   b->h ^= 1;
@@ -442,11 +443,15 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
     b->own_stream = true;
   }
   b->block = D0.block ? D0.block : 256;
+  if (D0.persistent) {
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    b->persist_blocks = std::max(8, step_occupancy(b->block) * cus);
+  }
   b->record = D0.record_forces ? 1 : 0;
   b->R = std::max(1, D0.rebuild_every);
   b->skin = b->R > 1 ? D0.skin : 0.f;
-  const double band = D0.band_ratio > 0.f ? D0.band_ratio : 2.0;
-  const double cfac = D0.cell_factor > 0.f ? D0.cell_factor : 1.0;
 
   // plan beds
   std::vector<LevelGrid> levels;
@@ -461,6 +466,8 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
     H.p0 = p;
     H.npad = (D->n + PAD - 1) / PAD * PAD;
     p += H.npad;
+    const double band = D->band_ratio > 0.f ? D->band_ratio : 2.0;
+    const double cfac = D->cell_factor > 0.f ? D->cell_factor : 1.0;
     plan_bed(D, band, cfac, (double)b->skin, H, levels, cell_base, lev_of[q]);
     H.nwall = D->n_walls;
     H.nbody = std::max(1, D->n_bodies);
@@ -738,7 +745,7 @@ lpr_status lpr_step_profiled(lpr_bed* b, int64_t n_steps, double out[4]) {
     if (b->since >= b->R) enqueue_rebuild(b);
     HIPTRY(hipEventRecord(ev[4 * q + 1], b->stream));
     StepPar p{b->s, b->h, b->l, false};
-    launch_step(b->d, p, b->block, b->record, b->stream);
+    launch_step(b->d, p, b->block, b->record, b->persist_blocks, b->stream);
     HIPTRY(hipEventRecord(ev[4 * q + 2], b->stream));
     launch_advance(b->d, b->block, b->stream);
     HIPTRY(hipEventRecord(ev[4 * q + 3], b->stream));
@@ -768,12 +775,12 @@ lpr_status lpr_sync(lpr_bed* b) {
   return sync_check(b);
 }
 
-lpr_status lpr_get_state(lpr_bed* b, double* pos, float* vel, float* omega) {
+static lpr_status get_state_impl(lpr_bed* b, int32_t bed, double* pos, float* vel, float* omega) {
   if (!b) return fail(LPR_E_INVAL, "null bed");
   int par = 0;
   lpr_status st = state_parity(b, &par);
   if (st != LPR_OK) return st;
-  const HostBed& H = b->hb[0];
+  const HostBed& H = b->hb[bed];
   std::vector<double4> hp(H.npad);
   std::vector<float4> hv(H.npad), hw(H.npad);
   HIPTRY(hipMemcpy(hp.data(), b->d.pos[par] + H.p0, sizeof(double4) * H.npad, hipMemcpyDeviceToHost));
@@ -788,10 +795,10 @@ lpr_status lpr_get_state(lpr_bed* b, double* pos, float* vel, float* omega) {
   return LPR_OK;
 }
 
-lpr_status lpr_set_state(lpr_bed* b, const double* pos, const float* vel, const float* omega) {
+static lpr_status set_state_impl(lpr_bed* b, int32_t bed, const double* pos, const float* vel, const float* omega) {
   lpr_status g = guard(b);
   if (g != LPR_OK) return g;
-  const HostBed& H = b->hb[0];
+  const HostBed& H = b->hb[bed];
   if (pos && !finite_arr(pos, 3 * H.n)) return fail(LPR_E_INVAL, "non-finite position");
   if (vel && !finite_arrf(vel, 3 * H.n)) return fail(LPR_E_INVAL, "non-finite velocity");
   if (omega && !finite_arrf(omega, 3 * H.n)) return fail(LPR_E_INVAL, "non-finite angular velocity");
@@ -816,11 +823,11 @@ lpr_status lpr_set_state(lpr_bed* b, const double* pos, const float* vel, const 
   return LPR_OK;
 }
 
-lpr_status lpr_get_history(lpr_bed* b, lpr_history* out, int64_t capacity, int64_t* n_total) {
+static lpr_status get_history_impl(lpr_bed* b, int32_t bed, lpr_history* out, int64_t capacity, int64_t* n_total) {
   if (!b) return fail(LPR_E_INVAL, "null bed");
   lpr_status st = sync_check(b);
   if (st != LPR_OK) return st;
-  const HostBed& H = b->hb[0];
+  const HostBed& H = b->hb[bed];
   const int64_t N = b->d.N;
   std::vector<int32_t> cnt(N), idx((size_t)K * N), sid(N);
   std::vector<uint32_t> fl(N);
@@ -859,14 +866,14 @@ lpr_status lpr_get_history(lpr_bed* b, lpr_history* out, int64_t capacity, int64
   return LPR_OK;
 }
 
-lpr_status lpr_set_history(lpr_bed* b, const lpr_history* rec, int64_t count) {
+static lpr_status set_history_impl(lpr_bed* b, int32_t bed, const lpr_history* rec, int64_t count) {
   lpr_status g = guard(b);
   if (g != LPR_OK) return g;
   if (count < 0 || (count > 0 && !rec)) return fail(LPR_E_INVAL, "bad history records");
   ensure_lists(b);
   lpr_status st = sync_check(b);
   if (st != LPR_OK) return st;
-  const HostBed& H = b->hb[0];
+  const HostBed& H = b->hb[bed];
   const int64_t N = b->d.N;
   std::vector<int32_t> cnt(N), idx((size_t)K * N), sid(N);
   HIPTRY(hipMemcpy(cnt.data(), b->d.own_cnt[b->l], sizeof(int32_t) * N, hipMemcpyDeviceToHost));
@@ -908,11 +915,11 @@ lpr_status lpr_set_history(lpr_bed* b, const lpr_history* rec, int64_t count) {
   return LPR_OK;
 }
 
-lpr_status lpr_read_contacts(lpr_bed* b, lpr_contact* out, int64_t capacity, int64_t* n_total) {
+static lpr_status read_contacts_impl(lpr_bed* b, int32_t bed, lpr_contact* out, int64_t capacity, int64_t* n_total) {
   if (!b) return fail(LPR_E_INVAL, "null bed");
   lpr_status st = sync_check(b);
   if (st != LPR_OK) return st;
-  const HostBed& H = b->hb[0];
+  const HostBed& H = b->hb[bed];
   const int64_t N = b->d.N;
   std::vector<int32_t> cnt(N), idx((size_t)K * N), sid(N);
   std::vector<uint32_t> fl(N);
@@ -941,12 +948,12 @@ lpr_status lpr_read_contacts(lpr_bed* b, lpr_contact* out, int64_t capacity, int
   return LPR_OK;
 }
 
-lpr_status lpr_read_forces(lpr_bed* b, float* force, float* torque) {
+static lpr_status read_forces_impl(lpr_bed* b, int32_t bed, float* force, float* torque) {
   if (!b) return fail(LPR_E_INVAL, "null bed");
   if (!b->record) return fail(LPR_E_STATE, "bed was created without record_forces");
   lpr_status st = sync_check(b);
   if (st != LPR_OK) return st;
-  const HostBed& H = b->hb[0];
+  const HostBed& H = b->hb[bed];
   std::vector<float4> f(H.npad), t(H.npad);
   HIPTRY(hipMemcpy(f.data(), b->d.frc + H.p0, sizeof(float4) * H.npad, hipMemcpyDeviceToHost));
   HIPTRY(hipMemcpy(t.data(), b->d.trq + H.p0, sizeof(float4) * H.npad, hipMemcpyDeviceToHost));
@@ -958,9 +965,9 @@ lpr_status lpr_read_forces(lpr_bed* b, float* force, float* torque) {
   return LPR_OK;
 }
 
-lpr_status lpr_read_reaction(lpr_bed* b, int32_t body, double out6[6]) {
+static lpr_status read_reaction_impl(lpr_bed* b, int32_t bed, int32_t body, double out6[6]) {
   if (!b || !out6) return fail(LPR_E_INVAL, "null argument");
-  const HostBed& H = b->hb[0];
+  const HostBed& H = b->hb[bed];
   if (body < 0 || body >= H.nbody) return fail(LPR_E_INVAL, "body out of range");
   lpr_status st = sync_check(b);
   if (st != LPR_OK) return st;
@@ -970,9 +977,9 @@ lpr_status lpr_read_reaction(lpr_bed* b, int32_t body, double out6[6]) {
   return LPR_OK;
 }
 
-lpr_status lpr_reaction_window(lpr_bed* b, int32_t body, double sum6[6], int64_t* steps, int32_t reset) {
+static lpr_status reaction_window_impl(lpr_bed* b, int32_t bed, int32_t body, double sum6[6], int64_t* steps, int32_t reset) {
   if (!b) return fail(LPR_E_INVAL, "null bed");
-  const HostBed& H = b->hb[0];
+  const HostBed& H = b->hb[bed];
   if (body < 0 || body >= H.nbody) return fail(LPR_E_INVAL, "body out of range");
   lpr_status st = sync_check(b);
   if (st != LPR_OK) return st;
@@ -989,9 +996,9 @@ lpr_status lpr_reaction_window(lpr_bed* b, int32_t body, double sum6[6], int64_t
   return LPR_OK;
 }
 
-lpr_status lpr_read_body(lpr_bed* b, int32_t body, double origin[3], double vel[3]) {
+static lpr_status read_body_impl(lpr_bed* b, int32_t bed, int32_t body, double origin[3], double vel[3]) {
   if (!b) return fail(LPR_E_INVAL, "null bed");
-  const HostBed& H = b->hb[0];
+  const HostBed& H = b->hb[bed];
   if (body < 0 || body >= H.nbody) return fail(LPR_E_INVAL, "body out of range");
   HIPTRY(hipStreamSynchronize(b->stream));
   BodyDyn D;
@@ -999,7 +1006,7 @@ lpr_status lpr_read_body(lpr_bed* b, int32_t body, double origin[3], double vel[
   BedDyn E;
   HIPTRY(hipMemcpy(&D, b->d.bdyn + H.body0 + body, sizeof(BodyDyn), hipMemcpyDeviceToHost));
   HIPTRY(hipMemcpy(&B, b->d.bdefs + H.body0 + body, sizeof(BodyDef), hipMemcpyDeviceToHost));
-  HIPTRY(hipMemcpy(&E, b->d.bedyn, sizeof(BedDyn), hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(&E, b->d.bedyn + bed, sizeof(BedDyn), hipMemcpyDeviceToHost));
   const double t = (double)E.k * H.dt;
   for (int a = 0; a < 3; ++a) {
     if (origin) origin[a] = B.origin[a] + B.lin_vel[a] * t;
@@ -1012,33 +1019,33 @@ lpr_status lpr_read_body(lpr_bed* b, int32_t body, double origin[3], double vel[
   return LPR_OK;
 }
 
-lpr_status lpr_set_clock(lpr_bed* b, int64_t step) {
+static lpr_status set_clock_impl(lpr_bed* b, int32_t bed, int64_t step) {
   lpr_status g = guard(b);
   if (g != LPR_OK) return g;
   if (step < 0) return fail(LPR_E_INVAL, "step must be >= 0");
   HIPTRY(hipStreamSynchronize(b->stream));
   BedDyn E;
-  HIPTRY(hipMemcpy(&E, b->d.bedyn, sizeof(BedDyn), hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(&E, b->d.bedyn + bed, sizeof(BedDyn), hipMemcpyDeviceToHost));
   E.k = step;
-  HIPTRY(hipMemcpy(b->d.bedyn, &E, sizeof(BedDyn), hipMemcpyHostToDevice));
+  HIPTRY(hipMemcpy(b->d.bedyn + bed, &E, sizeof(BedDyn), hipMemcpyHostToDevice));
   launch_poses(b->d, b->stream);
   HIPTRY(hipStreamSynchronize(b->stream));
   return LPR_OK;
 }
 
-lpr_status lpr_get_clock(lpr_bed* b, int64_t* step) {
+static lpr_status get_clock_impl(lpr_bed* b, int32_t bed, int64_t* step) {
   if (!b || !step) return fail(LPR_E_INVAL, "null argument");
   HIPTRY(hipStreamSynchronize(b->stream));
   BedDyn E;
-  HIPTRY(hipMemcpy(&E, b->d.bedyn, sizeof(BedDyn), hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(&E, b->d.bedyn + bed, sizeof(BedDyn), hipMemcpyDeviceToHost));
   *step = E.k;
   return LPR_OK;
 }
 
-lpr_status lpr_set_body_state(lpr_bed* b, int32_t body, double z, double vz) {
+static lpr_status set_body_state_impl(lpr_bed* b, int32_t bed, int32_t body, double z, double vz) {
   lpr_status g = guard(b);
   if (g != LPR_OK) return g;
-  const HostBed& H = b->hb[0];
+  const HostBed& H = b->hb[bed];
   if (body < 0 || body >= H.nbody) return fail(LPR_E_INVAL, "body out of range");
   HIPTRY(hipStreamSynchronize(b->stream));
   BodyDyn D;
@@ -1077,6 +1084,191 @@ lpr_status lpr_get_stats(lpr_bed* b, lpr_stats* out) {
   out->max_owner_slots = (int32_t)stat[0];
   out->skin_trips = b->skin_trips;
   return LPR_OK;
+}
+
+
+lpr_status lpr_batch_create(const lpr_bed_desc* const* descs, int32_t n_beds, const lpr_allocator* alloc,
+                            void* hip_stream, lpr_bed** out) {
+  if (n_beds <= 0 || n_beds > (1 << 20)) {
+    if (out) *out = nullptr;
+    return fail(LPR_E_INVAL, "n_beds out of range");
+  }
+  for (int q = 1; q < n_beds; ++q)
+    if (!descs || !descs[q] || !descs[0] || descs[q]->rebuild_every != descs[0]->rebuild_every ||
+        descs[q]->skin != descs[0]->skin || descs[q]->block != descs[0]->block ||
+        descs[q]->record_forces != descs[0]->record_forces || descs[q]->persistent != descs[0]->persistent)
+      return fail(LPR_E_INVAL, "beds of a batch share rebuild_every, skin, block, persistent, record_forces");
+  return create_impl(descs, n_beds, alloc, hip_stream, out);
+}
+
+lpr_status lpr_batch_size(lpr_bed* b, int32_t* n_beds) {
+  if (!b || !n_beds) return fail(LPR_E_INVAL, "null argument");
+  *n_beds = (int32_t)b->hb.size();
+  return LPR_OK;
+}
+
+lpr_status lpr_set_launch(lpr_bed* b, int32_t block, int32_t persistent) {
+  lpr_status g = guard(b);
+  if (g != LPR_OK) return g;
+  if (block != 64 && block != 128 && block != 256) return fail(LPR_E_INVAL, "block must be 64, 128 or 256");
+  HIPTRY(hipStreamSynchronize(b->stream));
+  b->block = block;
+  b->persist_blocks = 0;
+  if (persistent) {
+    int dev = 0, cus = 0;
+    HIPTRY(hipGetDevice(&dev));
+    HIPTRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    b->persist_blocks = std::max(8, step_occupancy(block) * cus);
+  }
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->has_graph = false;
+  return LPR_OK;
+}
+
+namespace {
+
+lpr_status time_trial(lpr_bed* b, int32_t steps, double* ms_per_step) {
+  lpr_status st = lpr_step(b, 2);  // first rebuild and graph capture outside the timing
+  if (st == LPR_OK) st = lpr_sync(b);
+  double out[4];
+  if (st == LPR_OK) st = lpr_step_profiled(b, steps, out);
+  if (st == LPR_OK) *ms_per_step = out[3] / steps;
+  return st;
+}
+
+}  // namespace
+
+lpr_status lpr_autotune(const lpr_bed_desc* const* descs, int32_t n_beds, const lpr_allocator* alloc,
+                        void* hip_stream, int32_t trial_steps, lpr_tuning* best, lpr_tuning* trials,
+                        int32_t capacity, int32_t* n_trials) {
+  if (!descs || n_beds <= 0 || !best || trial_steps <= 0) return fail(LPR_E_INVAL, "bad arguments");
+  std::vector<lpr_bed_desc> work(descs[0] ? (size_t)n_beds : 0);
+  for (int q = 0; q < n_beds; ++q) {
+    if (!descs[q]) return fail(LPR_E_INVAL, "null description");
+    work[q] = *descs[q];
+  }
+  std::vector<const lpr_bed_desc*> ptrs(n_beds);
+  for (int q = 0; q < n_beds; ++q) ptrs[q] = &work[q];
+  std::vector<lpr_tuning> done;
+  // layout: radius-band ratio and cell factor (one batch each)
+  const float bands[3] = {1.5f, 2.0f, 3.0f};
+  const float cells[2] = {1.0f, 1.25f};
+  lpr_tuning bestt{};
+  bestt.ms_per_step = std::numeric_limits<double>::max();
+  for (float br : bands)
+    for (float cf : cells) {
+      for (auto& w : work) {
+        w.band_ratio = br;
+        w.cell_factor = cf;
+        w.block = 256;
+        w.persistent = 0;
+        w.record_forces = 0;
+      }
+      lpr_bed* b = nullptr;
+      lpr_status st = create_impl(ptrs.data(), n_beds, alloc, hip_stream, &b);
+      if (st != LPR_OK) return st;
+      double ms = 0.0;
+      st = time_trial(b, trial_steps, &ms);
+      lpr_bed_destroy(b);
+      if (st != LPR_OK) return st;
+      lpr_tuning t{br, cf, 256, 0, ms};
+      done.push_back(t);
+      if (ms < bestt.ms_per_step) bestt = t;
+    }
+  // launch shape on the chosen layout
+  for (auto& w : work) {
+    w.band_ratio = bestt.band_ratio;
+    w.cell_factor = bestt.cell_factor;
+  }
+  lpr_bed* b = nullptr;
+  lpr_status st = create_impl(ptrs.data(), n_beds, alloc, hip_stream, &b);
+  if (st != LPR_OK) return st;
+  const int blocks[3] = {64, 128, 256};
+  for (int bl : blocks)
+    for (int pe = 0; pe < 2; ++pe) {
+      if (bl == 256 && pe == 0) continue;  // measured in the layout phase
+      st = lpr_set_launch(b, bl, pe);
+      double ms = 0.0;
+      if (st == LPR_OK) st = time_trial(b, trial_steps, &ms);
+      if (st != LPR_OK) {
+        lpr_bed_destroy(b);
+        return st;
+      }
+      lpr_tuning t{bestt.band_ratio, bestt.cell_factor, bl, pe, ms};
+      done.push_back(t);
+      if (ms < bestt.ms_per_step) bestt = t;
+    }
+  lpr_bed_destroy(b);
+  *best = bestt;
+  if (n_trials) *n_trials = (int32_t)done.size();
+  if (trials)
+    for (int q = 0; q < (int)done.size() && q < capacity; ++q) trials[q] = done[q];
+  return LPR_OK;
+}
+
+// Single-bed entry points address bed 0; the batch ones take a bed index.
+lpr_status lpr_get_state(lpr_bed* b, double* pos, float* vel, float* omega) { return get_state_impl(b, 0, pos, vel, omega); }
+lpr_status lpr_batch_get_state(lpr_bed* b, int32_t bed, double* pos, float* vel, float* omega) {
+  if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
+  return get_state_impl(b, bed, pos, vel, omega);
+}
+lpr_status lpr_set_state(lpr_bed* b, const double* pos, const float* vel, const float* omega) { return set_state_impl(b, 0, pos, vel, omega); }
+lpr_status lpr_batch_set_state(lpr_bed* b, int32_t bed, const double* pos, const float* vel, const float* omega) {
+  if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
+  return set_state_impl(b, bed, pos, vel, omega);
+}
+lpr_status lpr_get_history(lpr_bed* b, lpr_history* out, int64_t capacity, int64_t* n_total) { return get_history_impl(b, 0, out, capacity, n_total); }
+lpr_status lpr_batch_get_history(lpr_bed* b, int32_t bed, lpr_history* out, int64_t capacity, int64_t* n_total) {
+  if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
+  return get_history_impl(b, bed, out, capacity, n_total);
+}
+lpr_status lpr_set_history(lpr_bed* b, const lpr_history* rec, int64_t count) { return set_history_impl(b, 0, rec, count); }
+lpr_status lpr_batch_set_history(lpr_bed* b, int32_t bed, const lpr_history* rec, int64_t count) {
+  if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
+  return set_history_impl(b, bed, rec, count);
+}
+lpr_status lpr_read_contacts(lpr_bed* b, lpr_contact* out, int64_t capacity, int64_t* n_total) { return read_contacts_impl(b, 0, out, capacity, n_total); }
+lpr_status lpr_batch_read_contacts(lpr_bed* b, int32_t bed, lpr_contact* out, int64_t capacity, int64_t* n_total) {
+  if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
+  return read_contacts_impl(b, bed, out, capacity, n_total);
+}
+lpr_status lpr_read_forces(lpr_bed* b, float* force, float* torque) { return read_forces_impl(b, 0, force, torque); }
+lpr_status lpr_batch_read_forces(lpr_bed* b, int32_t bed, float* force, float* torque) {
+  if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
+  return read_forces_impl(b, bed, force, torque);
+}
+lpr_status lpr_read_reaction(lpr_bed* b, int32_t body, double out6[6]) { return read_reaction_impl(b, 0, body, out6); }
+lpr_status lpr_batch_read_reaction(lpr_bed* b, int32_t bed, int32_t body, double out6[6]) {
+  if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
+  return read_reaction_impl(b, bed, body, out6);
+}
+lpr_status lpr_reaction_window(lpr_bed* b, int32_t body, double sum6[6], int64_t* steps, int32_t reset) { return reaction_window_impl(b, 0, body, sum6, steps, reset); }
+lpr_status lpr_batch_reaction_window(lpr_bed* b, int32_t bed, int32_t body, double sum6[6], int64_t* steps, int32_t reset) {
+  if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
+  return reaction_window_impl(b, bed, body, sum6, steps, reset);
+}
+lpr_status lpr_read_body(lpr_bed* b, int32_t body, double origin[3], double vel[3]) { return read_body_impl(b, 0, body, origin, vel); }
+lpr_status lpr_batch_read_body(lpr_bed* b, int32_t bed, int32_t body, double origin[3], double vel[3]) {
+  if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
+  return read_body_impl(b, bed, body, origin, vel);
+}
+lpr_status lpr_set_clock(lpr_bed* b, int64_t step) { return set_clock_impl(b, 0, step); }
+lpr_status lpr_batch_set_clock(lpr_bed* b, int32_t bed, int64_t step) {
+  if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
+  return set_clock_impl(b, bed, step);
+}
+lpr_status lpr_get_clock(lpr_bed* b, int64_t* step) { return get_clock_impl(b, 0, step); }
+lpr_status lpr_batch_get_clock(lpr_bed* b, int32_t bed, int64_t* step) {
+  if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
+  return get_clock_impl(b, bed, step);
+}
+lpr_status lpr_set_body_state(lpr_bed* b, int32_t body, double z, double vz) { return set_body_state_impl(b, 0, body, z, vz); }
+lpr_status lpr_batch_set_body_state(lpr_bed* b, int32_t bed, int32_t body, double z, double vz) {
+  if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
+  return set_body_state_impl(b, bed, body, z, vz);
 }
 
 }  // extern "C"

@@ -24,10 +24,11 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device erro
           -5: "invalid state", -6: "non-finite value"}
 
 # Entry points declared in include/lprdem.h
-SYMBOLS = ("lpr_bed_create", "lpr_bed_destroy", "lpr_step", "lpr_step_profiled", "lpr_sync", "lpr_get_state", "lpr_set_state",
-           "lpr_get_history", "lpr_set_history", "lpr_read_contacts", "lpr_read_forces", "lpr_read_reaction",
-           "lpr_reaction_window", "lpr_read_body", "lpr_set_clock", "lpr_get_clock", "lpr_set_body_state",
-           "lpr_get_stats", "lpr_status_str", "lpr_last_error")
+_PER_BED = ("get_state", "set_state", "get_history", "set_history", "read_contacts", "read_forces", "read_reaction",
+            "reaction_window", "read_body", "set_clock", "get_clock", "set_body_state")
+SYMBOLS = ("lpr_bed_create", "lpr_bed_destroy", "lpr_step", "lpr_step_profiled", "lpr_sync", "lpr_get_stats",
+           "lpr_status_str", "lpr_last_error", "lpr_batch_create", "lpr_batch_size", "lpr_set_launch",
+           "lpr_autotune") + tuple("lpr_" + f for f in _PER_BED) + tuple("lpr_batch_" + f for f in _PER_BED)
 
 
 class LprError(RuntimeError):
@@ -68,7 +69,8 @@ class _Desc(ctypes.Structure):
                 ("omega", ctypes.c_void_p), ("n_walls", ctypes.c_int32), ("walls", ctypes.c_void_p),
                 ("n_bodies", ctypes.c_int32), ("bodies", ctypes.c_void_p), ("params", _Params),
                 ("rebuild_every", ctypes.c_int32), ("skin", ctypes.c_float), ("band_ratio", ctypes.c_float),
-                ("cell_factor", ctypes.c_float), ("block", ctypes.c_int32), ("record_forces", ctypes.c_int32)]
+                ("cell_factor", ctypes.c_float), ("block", ctypes.c_int32), ("record_forces", ctypes.c_int32),
+                ("persistent", ctypes.c_int32)]
 
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
@@ -86,6 +88,11 @@ class _Contact(ctypes.Structure):
 class _History(ctypes.Structure):
     _fields_ = [("owner", ctypes.c_int64), ("partner", ctypes.c_int64), ("xi_t", ctypes.c_float * 3),
                 ("xi_r", ctypes.c_float * 3)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("band_ratio", ctypes.c_float), ("cell_factor", ctypes.c_float), ("block", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -119,6 +126,15 @@ def load_library(path: str = LIB_PATH):
         "lpr_read_body": [vp, i32, vp, vp], "lpr_set_clock": [vp, i64], "lpr_get_clock": [vp, ctypes.POINTER(i64)],
         "lpr_set_body_state": [vp, i32, d, d], "lpr_get_stats": [vp, ctypes.POINTER(_Stats)],
     }
+    for f in _PER_BED:
+        args = sig["lpr_" + f]
+        sig["lpr_batch_" + f] = [args[0], i32] + args[1:]
+    sig["lpr_batch_create"] = [ctypes.POINTER(ctypes.POINTER(_Desc)), i32, ctypes.POINTER(_Allocator), vp,
+                               ctypes.POINTER(vp)]
+    sig["lpr_batch_size"] = [vp, ctypes.POINTER(i32)]
+    sig["lpr_set_launch"] = [vp, i32, i32]
+    sig["lpr_autotune"] = [ctypes.POINTER(ctypes.POINTER(_Desc)), i32, ctypes.POINTER(_Allocator), vp, i32,
+                           ctypes.POINTER(_Tuning), ctypes.POINTER(_Tuning), i32, ctypes.POINTER(i32)]
     for name, args in sig.items():
         f = getattr(L, name)
         f.restype = ctypes.c_int
@@ -158,7 +174,7 @@ def _ptr(a):
 class _DescHolder:
     """A filled lpr_bed_desc plus the arrays it points to (kept alive)."""
 
-    def __init__(self, spec, rebuild_every, skin, band_ratio, cell_factor, block, record_forces):
+    def __init__(self, spec, rebuild_every, skin, band_ratio, cell_factor, block, record_forces, persistent=False):
         self.pos = np.ascontiguousarray(spec.pos, np.float64)
         self.rad = np.ascontiguousarray(spec.radius, np.float32)
         self.vel = np.ascontiguousarray(spec.vel, np.float32)
@@ -195,34 +211,20 @@ class _DescHolder:
         D.cell_factor = float(cell_factor)
         D.block = int(block)
         D.record_forces = 1 if record_forces else 0
+        D.persistent = 1 if persistent else 0
         self.desc = D
 
 
-class Bed:
-    """A graded bed stepped by the HIP library on one GPU.
+class _TorchMemory:
+    """Allocator callbacks into torch's caching allocator on one stream."""
 
-    spec: paper_2501_05300_amd.beds.BedSpec.  rebuild_every / skin /
-    band_ratio / cell_factor / block choose how contacts are found (never
-    which); record_forces keeps per-particle contact forces for forces().
-    """
-
-    def __init__(self, spec, rebuild_every=1, skin=0.0, band_ratio=0.0, cell_factor=0.0, block=0,
-                 record_forces=False, device=0, torch_memory=True):
+    def __init__(self, device, stream):
         import torch
-        if not torch.cuda.is_available():
-            raise RuntimeError("the HIP stepper needs a GPU (torch.cuda.is_available() is False)")
-        L = load_library()
-        self.spec = spec
-        self.n = spec.n
-        self.device = torch.device("cuda", device)
-        self.stream = torch.cuda.Stream(self.device)
-        self._holder = _DescHolder(spec, rebuild_every, skin, band_ratio, cell_factor, block, record_forces)
         self._live = {}
-        dev, stream = self.device, self.stream
 
         def _alloc(ctx, nbytes):
             try:
-                p = torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
             except Exception:  # noqa: BLE001  (reported to the library as NULL)
                 return None
             self._live[p] = nbytes
@@ -234,14 +236,27 @@ class Bed:
                 torch.cuda.caching_allocator_delete(p)
 
         self._cb = (_ALLOC(_alloc), _RELEASE(_release))
-        self._alloc = _Allocator(self._cb[0], self._cb[1], None)
-        h = ctypes.c_void_p()
-        with torch.cuda.device(self.device):
-            rc = L.lpr_bed_create(ctypes.byref(self._holder.desc),
-                                  ctypes.byref(self._alloc) if torch_memory else None,
-                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
-        _check(rc, "lpr_bed_create")
-        self._h = h
+        self.struct = _Allocator(self._cb[0], self._cb[1], None)
+
+
+def _gpu_or_raise(device):
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the HIP stepper needs a GPU (torch.cuda.is_available() is False)")
+    return torch.device("cuda", device)
+
+
+class _Stepper:
+    """Common part of Bed and Batch: stepping and the per-bed reads."""
+
+    _batch = False
+
+    def _call(self, name, bed, *args):
+        if self._batch:
+            return _check(getattr(_lib, "lpr_batch_" + name)(self._h, int(bed), *args), "lpr_batch_" + name)
+        if bed != 0:
+            raise IndexError("a single bed has index 0")
+        return _check(getattr(_lib, "lpr_" + name)(self._h, *args), "lpr_" + name)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -268,34 +283,43 @@ class Bed:
     def sync(self):
         _check(_lib.lpr_sync(self._h), "lpr_sync")
 
+    def set_launch(self, block, persistent=False):
+        _check(_lib.lpr_set_launch(self._h, int(block), 1 if persistent else 0), "lpr_set_launch")
+
+    def stats(self):
+        s = _Stats()
+        _check(_lib.lpr_get_stats(self._h, ctypes.byref(s)), "lpr_get_stats")
+        return {f: getattr(s, f) for f, _ in _Stats._fields_}
+
     # state
-    def state(self):
-        pos = np.zeros((self.n, 3), np.float64)
-        vel = np.zeros((self.n, 3), np.float32)
-        omg = np.zeros((self.n, 3), np.float32)
-        _check(_lib.lpr_get_state(self._h, _ptr(pos), _ptr(vel), _ptr(omg)), "lpr_get_state")
+    def state(self, bed=0):
+        n = self._n(bed)
+        pos = np.zeros((n, 3), np.float64)
+        vel = np.zeros((n, 3), np.float32)
+        omg = np.zeros((n, 3), np.float32)
+        self._call("get_state", bed, _ptr(pos), _ptr(vel), _ptr(omg))
         return pos, vel, omg
 
-    def set_state(self, pos=None, vel=None, omg=None):
+    def set_state(self, pos=None, vel=None, omg=None, bed=0):
         c64 = lambda a: None if a is None else np.ascontiguousarray(a, np.float64).reshape(-1, 3)
         c32 = lambda a: None if a is None else np.ascontiguousarray(a, np.float32).reshape(-1, 3)
         pos, vel, omg = c64(pos), c32(vel), c32(omg)
-        _check(_lib.lpr_set_state(self._h, _ptr(pos), _ptr(vel), _ptr(omg)), "lpr_set_state")
+        self._call("set_state", bed, _ptr(pos), _ptr(vel), _ptr(omg))
 
-    def history(self):
+    def history(self, bed=0):
         """(keys (k, 2) int64 owner/partner code, values (k, 6) float32)."""
         tot = ctypes.c_int64(0)
-        rc = _lib.lpr_get_history(self._h, None, 0, ctypes.byref(tot))
-        if rc not in (0, -4):
-            _check(rc, "lpr_get_history")
+        try:
+            self._call("get_history", bed, None, 0, ctypes.byref(tot))
+        except CapacityError:
+            pass
         buf = (_History * max(1, tot.value))()
-        _check(_lib.lpr_get_history(self._h, ctypes.addressof(buf), tot.value, ctypes.byref(tot)),
-               "lpr_get_history")
+        self._call("get_history", bed, ctypes.addressof(buf), tot.value, ctypes.byref(tot))
         arr = np.frombuffer(buf, dtype=np.dtype([("o", "<i8"), ("p", "<i8"), ("v", "<f4", (6,))]),
                             count=tot.value)
         return np.stack([arr["o"], arr["p"]], 1), arr["v"].copy()
 
-    def set_history(self, keys, vals):
+    def set_history(self, keys, vals, bed=0):
         keys = np.asarray(keys, np.int64).reshape(-1, 2)
         vals = np.asarray(vals, np.float32).reshape(-1, 6)
         buf = (_History * max(1, len(keys)))()
@@ -304,56 +328,140 @@ class Bed:
             for a in range(3):
                 buf[q].xi_t[a] = float(vals[q, a])
                 buf[q].xi_r[a] = float(vals[q, 3 + a])
-        _check(_lib.lpr_set_history(self._h, ctypes.addressof(buf), len(keys)), "lpr_set_history")
+        self._call("set_history", bed, ctypes.addressof(buf), len(keys))
 
     # results of the last step
-    def contacts(self):
+    def contacts(self, bed=0):
         """(k, 2) int64: particle pairs (a < b stable ids) and wall contacts
         (particle, -1 - wall), ascending."""
         tot = ctypes.c_int64(0)
-        rc = _lib.lpr_read_contacts(self._h, None, 0, ctypes.byref(tot))
-        if rc not in (0, -4):
-            _check(rc, "lpr_read_contacts")
+        try:
+            self._call("read_contacts", bed, None, 0, ctypes.byref(tot))
+        except CapacityError:
+            pass
         out = np.zeros((max(1, tot.value), 2), np.int64)
-        _check(_lib.lpr_read_contacts(self._h, _ptr(out), tot.value, ctypes.byref(tot)), "lpr_read_contacts")
+        self._call("read_contacts", bed, _ptr(out), tot.value, ctypes.byref(tot))
         return out[:tot.value]
 
-    def forces(self):
-        F = np.zeros((self.n, 3), np.float32)
-        T = np.zeros((self.n, 3), np.float32)
-        _check(_lib.lpr_read_forces(self._h, _ptr(F), _ptr(T)), "lpr_read_forces")
+    def forces(self, bed=0):
+        n = self._n(bed)
+        F = np.zeros((n, 3), np.float32)
+        T = np.zeros((n, 3), np.float32)
+        self._call("read_forces", bed, _ptr(F), _ptr(T))
         return F, T
 
-    def reaction(self, body):
+    def reaction(self, body, bed=0):
         out = np.zeros(6)
-        _check(_lib.lpr_read_reaction(self._h, int(body), _ptr(out)), "lpr_read_reaction")
+        self._call("read_reaction", bed, int(body), _ptr(out))
         return out
 
-    def reaction_window(self, body, reset=False):
+    def reaction_window(self, body, reset=False, bed=0):
         s = np.zeros(6)
         k = ctypes.c_int64(0)
-        _check(_lib.lpr_reaction_window(self._h, int(body), _ptr(s), ctypes.byref(k), 1 if reset else 0),
-               "lpr_reaction_window")
+        self._call("reaction_window", bed, int(body), _ptr(s), ctypes.byref(k), 1 if reset else 0)
         return s, k.value
 
-    def body(self, body):
+    def body(self, body, bed=0):
         o = np.zeros(3)
         v = np.zeros(3)
-        _check(_lib.lpr_read_body(self._h, int(body), _ptr(o), _ptr(v)), "lpr_read_body")
+        self._call("read_body", bed, int(body), _ptr(o), _ptr(v))
         return o, v
 
-    def set_clock(self, step):
-        _check(_lib.lpr_set_clock(self._h, int(step)), "lpr_set_clock")
+    def set_clock(self, step, bed=0):
+        self._call("set_clock", bed, int(step))
 
-    def clock(self):
+    def clock(self, bed=0):
         k = ctypes.c_int64(0)
-        _check(_lib.lpr_get_clock(self._h, ctypes.byref(k)), "lpr_get_clock")
+        self._call("get_clock", bed, ctypes.byref(k))
         return k.value
 
-    def set_body_state(self, body, z, vz):
-        _check(_lib.lpr_set_body_state(self._h, int(body), float(z), float(vz)), "lpr_set_body_state")
+    def set_body_state(self, body, z, vz, bed=0):
+        self._call("set_body_state", bed, int(body), float(z), float(vz))
 
-    def stats(self):
-        s = _Stats()
-        _check(_lib.lpr_get_stats(self._h, ctypes.byref(s)), "lpr_get_stats")
-        return {f: getattr(s, f) for f, _ in _Stats._fields_}
+
+class Bed(_Stepper):
+    """A graded bed stepped by the HIP library on one GPU.
+
+    spec: paper_2501_05300_amd.beds.BedSpec.  rebuild_every / skin /
+    band_ratio / cell_factor / block / persistent choose how contacts are
+    found and how the step kernel is launched (never which contacts or what
+    results); record_forces keeps per-particle contact forces for forces().
+    """
+
+    def __init__(self, spec, rebuild_every=1, skin=0.0, band_ratio=0.0, cell_factor=0.0, block=0,
+                 record_forces=False, persistent=False, device=0, torch_memory=True):
+        import torch
+        self.device = _gpu_or_raise(device)
+        L = load_library()
+        self.spec = spec
+        self.n = spec.n
+        self.stream = torch.cuda.Stream(self.device)
+        self._holder = _DescHolder(spec, rebuild_every, skin, band_ratio, cell_factor, block, record_forces,
+                                   persistent)
+        self._mem = _TorchMemory(self.device, self.stream)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = L.lpr_bed_create(ctypes.byref(self._holder.desc),
+                                  ctypes.byref(self._mem.struct) if torch_memory else None,
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        _check(rc, "lpr_bed_create")
+        self._h = h
+
+    def _n(self, bed):
+        return self.n
+
+
+class Batch(_Stepper):
+    """Many beds stepped together (one launch per kernel covers all beds)."""
+
+    _batch = True
+
+    def __init__(self, specs, rebuild_every=1, skin=0.0, band_ratio=0.0, cell_factor=0.0, block=0,
+                 record_forces=False, persistent=False, device=0, layouts=None):
+        import torch
+        self.device = _gpu_or_raise(device)
+        L = load_library()
+        self.specs = list(specs)
+        self.stream = torch.cuda.Stream(self.device)
+        self._holders = []
+        for q, s in enumerate(self.specs):
+            br, cf = (layouts[q] if layouts is not None else (band_ratio, cell_factor))
+            self._holders.append(_DescHolder(s, rebuild_every, skin, br, cf, block, record_forces, persistent))
+        arr = (ctypes.POINTER(_Desc) * len(self._holders))(*[ctypes.pointer(h.desc) for h in self._holders])
+        self._mem = _TorchMemory(self.device, self.stream)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = L.lpr_batch_create(arr, len(self._holders), ctypes.byref(self._mem.struct),
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        _check(rc, "lpr_batch_create")
+        self._h = h
+        self.n = sum(s.n for s in self.specs)
+
+    def _n(self, bed):
+        return self.specs[bed].n
+
+    def __len__(self):
+        n = ctypes.c_int32(0)
+        _check(_lib.lpr_batch_size(self._h, ctypes.byref(n)), "lpr_batch_size")
+        return n.value
+
+
+def autotune(specs, trial_steps=20, rebuild_every=1, skin=0.0, device=0):
+    """Runs the library's autotuner on copies of the beds; returns
+    (best setting, list of all trials) as dicts."""
+    import torch
+    dev = _gpu_or_raise(device)
+    L = load_library()
+    stream = torch.cuda.Stream(dev)
+    holders = [_DescHolder(s, rebuild_every, skin, 0.0, 0.0, 0, False) for s in specs]
+    arr = (ctypes.POINTER(_Desc) * len(holders))(*[ctypes.pointer(h.desc) for h in holders])
+    mem = _TorchMemory(dev, stream)
+    best = _Tuning()
+    trials = (_Tuning * 32)()
+    nt = ctypes.c_int32(0)
+    with torch.cuda.device(dev):
+        rc = L.lpr_autotune(arr, len(holders), ctypes.byref(mem.struct), ctypes.c_void_p(stream.cuda_stream),
+                            int(trial_steps), ctypes.byref(best), trials, 32, ctypes.byref(nt))
+    _check(rc, "lpr_autotune")
+    as_dict = lambda t: {f: getattr(t, f) for f, _ in _Tuning._fields_}
+    return as_dict(best), [as_dict(trials[q]) for q in range(nt.value)]
