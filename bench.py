@@ -78,7 +78,7 @@ def settle_beds(specs, steps, chunk=5000):
             w.mu_t, w.mu_r = 0.0, 0.0
         work.append(s)
     rmin = min(float(s.radius.min()) for s in specs)
-    sb = Batch(work, rebuild_every=10, skin=0.1 * rmin)
+    sb = Batch(work, rebuild_every=5, skin=0.25 * rmin)
     done = 0
     t0 = time.perf_counter()
     ntot = sum(s.n for s in specs)

@@ -458,19 +458,18 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
         in.xt = f3(0.f, 0.f, 0.f);
         in.xr = f3(0.f, 0.f, 0.f);
       }
-      double dist, nxd, nyd, nzd;
-      if (d2 > 0.0) {
-        dist = sqrt(d2);
-        const double id = 1.0 / dist;
-        nxd = dx * id; nyd = dy * id; nzd = dz * id;
-      } else {
-        dist = 0.0;
-        nxd = 0.0; nyd = 0.0; nzd = 1.0;
-      }
+      // overlap in FP64 (it is a small difference of large numbers); the
+      // unit normal only needs FP32
+      const double dist = sqrt(d2);
       const double dl = (xa.w + xb.w) - dist;
       const float ra = (float)xa.w, rb = (float)xb.w;
       in.delta = (float)dl;
-      in.n = f3((float)nxd, (float)nyd, (float)nzd);
+      if (d2 > 0.0) {
+        const float id = 1.0f / (float)dist;
+        in.n = f3((float)dx * id, (float)dy * id, (float)dz * id);
+      } else {
+        in.n = f3(0.f, 0.f, 1.f);
+      }
       const float la = ra - 0.5f * in.delta, lb = rb - 0.5f * in.delta;   // lever arms
       const float3 wa3 = f3(wa.x, wa.y, wa.z), wb3 = f3(wb.x, wb.y, wb.z);
       in.u = f3(va.x - vb.x, va.y - vb.y, va.z - vb.z) + la * cross(wa3, in.n) + lb * cross(wb3, in.n);

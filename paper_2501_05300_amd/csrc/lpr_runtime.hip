@@ -98,7 +98,8 @@ struct lpr_bed {
   int block = 256;
   int persist_blocks = 0;  // > 0: persistent step kernel with this grid
   int record = 0;
-  int R = 1;
+  int R = 1;      // configured rebuild cadence
+  int R_eff = 1;  // cadence in use (halved after a skin trip, restored per lpr_step)
   float skin = 0.f;
   // host parities
   int s = 0, h = 0, l = 0;
@@ -281,7 +282,7 @@ void set_par(lpr_bed* b, const Par& p) {
 }
 
 // Parity changes of one step, as enqueue_step makes them.
-void simulate_step(Par& p, int R) {
+void simulate_step(Par& p, int R) {  // R: the cadence of the captured cycle
   if (p.since >= R) {
     p.l ^= 1;
     p.h ^= 1;
@@ -325,6 +326,7 @@ lpr_status sync_check(lpr_bed* b) {
     b->base_par = cur_par(b);
     b->plog.clear();
     b->skin_trips += 1;
+    b->R_eff = std::max(1, b->R_eff / 2);  // rebuild more often for the rest of this call
     for (int64_t q = 0; q < remaining; ++q) enqueue_step(b);
     HIPTRY(hipGetLastError());
   }
@@ -360,7 +362,7 @@ void enqueue_rebuild(lpr_bed* b) {
 }
 
 void enqueue_step(lpr_bed* b) {
-  if (b->since >= b->R) enqueue_rebuild(b);
+  if (b->since >= b->R_eff) enqueue_rebuild(b);
   StepPar p{b->s, b->h, b->l, false};
   launch_step(b->d, p, b->block, b->record, b->persist_blocks, b->stream);
   launch_advance(b->d, b->block, b->stream);
@@ -401,7 +403,7 @@ lpr_status guard(lpr_bed* b) {
 }
 
 lpr_status ensure_lists(lpr_bed* b) {
-  if (b->since >= b->R) enqueue_rebuild(b);
+  if (b->since >= b->R_eff) enqueue_rebuild(b);
   return LPR_OK;
 }
 
@@ -451,6 +453,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   }
   b->record = D0.record_forces ? 1 : 0;
   b->R = std::max(1, D0.rebuild_every);
+  b->R_eff = b->R;
   b->skin = b->R > 1 ? D0.skin : 0.f;
 
   // plan beds
@@ -703,6 +706,7 @@ lpr_status lpr_step(lpr_bed* b, int64_t n_steps) {
   lpr_status g = guard(b);
   if (g != LPR_OK) return g;
   if (n_steps < 0) return fail(LPR_E_INVAL, "n_steps must be >= 0");
+  b->R_eff = b->R;
   while (n_steps > 0) {
     const bool at_cycle = (b->since >= b->R);
     if (at_cycle && n_steps >= 2 * b->R) {
@@ -742,7 +746,7 @@ lpr_status lpr_step_profiled(lpr_bed* b, int64_t n_steps, double out[4]) {
   for (auto& e : ev) HIPTRY(hipEventCreate(&e));
   for (int64_t q = 0; q < n_steps; ++q) {
     HIPTRY(hipEventRecord(ev[4 * q + 0], b->stream));
-    if (b->since >= b->R) enqueue_rebuild(b);
+    if (b->since >= b->R_eff) enqueue_rebuild(b);
     HIPTRY(hipEventRecord(ev[4 * q + 1], b->stream));
     StepPar p{b->s, b->h, b->l, false};
     launch_step(b->d, p, b->block, b->record, b->persist_blocks, b->stream);
