@@ -278,6 +278,33 @@ lpr_status lpr_autotune(const lpr_bed_desc* const* descs, int32_t n_beds, const 
                         void* hip_stream, int32_t trial_steps, lpr_tuning* best, lpr_tuning* trials,
                         int32_t capacity, int32_t* n_trials);
 
+/* ---- adjoint --------------------------------------------------------
+ * Calibration needs the sensitivity of bulk responses to the contact
+ * parameters (the paper's introduction: scaled DEM models must be
+ * calibrated; parameters k_n, mu_t, mu_r of its contact model).
+ *
+ * lpr_set_contact_params replaces (s_k, mu_t, mu_r) of every bed.
+ *
+ * lpr_adjoint_window steps a single bed n_steps steps from its current
+ * state and returns J = (1/n_steps) sum_k R_z(k), the mean z reaction on
+ * `body`, and dJ/d(s_k, mu_t, mu_r) by reverse mode: the window runs forward
+ * with a checkpoint every ckpt_every steps (candidate lists rebuilt at each
+ * checkpoint with a skin of max(skin, r_min/4) that must hold for the
+ * segment; otherwise LPR_E_STATE); then, segment by segment in reverse, the
+ * checkpoint is restored, the segment recomputed with its per-step inputs
+ * recorded, and the hand-written vector-Jacobian products of integration,
+ * accumulation, contact law and geometry run step by step, holding the
+ * contact set and the Coulomb / rolling / clamp branches as the forward took
+ * them.  State adjoints are FP32; parameter adjoints are summed in FP64.
+ * mu_t / mu_r act on particle-particle contacts and on walls whose mu is
+ * negative (they follow the bed).  The bed is left in its state after the
+ * window.  Bodies must be prescribed and non-rotating (LPR_E_INVAL).
+ * Device memory: about (ckpt_every + n_steps / ckpt_every) * 600 bytes per
+ * particle. */
+lpr_status lpr_set_contact_params(lpr_bed* bed, double s_k, double mu_t, double mu_r);
+lpr_status lpr_adjoint_window(lpr_bed* bed, int64_t n_steps, int32_t ckpt_every, int32_t body, double* J,
+                              double grad[3]);
+
 const char* lpr_status_str(lpr_status s);
 /* Message of the last error on the calling thread ("" if none). */
 const char* lpr_last_error(void);

@@ -53,7 +53,8 @@ struct BedConst {
   int32_t body0, nbody;
   int32_t p0, p1;        // padded particle range [p0, p1)
   float skin;
-  float bp_tol;          // FP32 broad-phase pre-test margin [m]
+  float bp_tol;
+  float s_k;             // stiffness multiplier (part of kfac)          // FP32 broad-phase pre-test margin [m]
   // contact law (FP32) and integration
   float kfac;            // s_k E* / 3  (k_n = kfac sqrt(d*))
   float gn;              // gamma_n = gamma_factor dt
@@ -258,56 +259,194 @@ struct LawOut {
   float3 xt, xr;     // updated springs
 };
 
-__device__ __forceinline__ void contact_law(const BedConst& bc, const LawIn& in, LawOut& o) {
-  const float kn = bc.kfac * sqrtf(in.dstar);
-  const float rstar = 0.5f * in.dstar;
-  const float dd = dot(in.u, in.n);
-  float a1, a0;
+// Intermediates of one law evaluation: everything its vector-Jacobian
+// product needs, including the branch taken at each cap and clamp.
+struct LawTape {
+  float kn, rstar, dd, a0, a1, Fn, kt, ct;
+  bool on;            // normal force before the clamp was positive
+  float3 vt;
+  float xn, lp2, sc;
+  float3 xp0;
+  bool rot;           // stored spring was rotated into the tangent plane
+  float3 xt1, Ftr;
+  float capt, Ft2;
+  bool slip;          // Coulomb cap active
+  float kr, cr;
+  float3 xr1, Mtr;
+  float capr, M2;
+  bool roll;          // rolling cap active
+};
+
+__device__ __forceinline__ void law_forward(const BedConst& bc, const LawIn& in, LawTape& t, LawOut& o) {
+  t.kn = bc.kfac * sqrtf(in.dstar);
+  t.rstar = 0.5f * in.dstar;
+  t.dd = dot(in.u, in.n);
   if (bc.law == 0) {
-    a0 = sqrtf(in.delta);
-    a1 = in.delta * a0;
+    t.a0 = sqrtf(in.delta);
+    t.a1 = in.delta * t.a0;
   } else if (bc.law == 1) {
-    a0 = 1.0f;
-    a1 = in.delta;
+    t.a0 = 1.0f;
+    t.a1 = in.delta;
   } else {
-    a0 = powf(in.delta, 2.0f * bc.eH - 2.0f);
-    a1 = powf(in.delta, 2.0f * bc.eH - 1.0f);
+    t.a0 = powf(in.delta, 2.0f * bc.eH - 2.0f);
+    t.a1 = powf(in.delta, 2.0f * bc.eH - 1.0f);
   }
-  float Fn = kn * (a1 + bc.eH * bc.gn * a0 * dd);
-  Fn = fmaxf(Fn, 0.0f);
+  const float Fr = t.kn * (t.a1 + bc.eH * bc.gn * t.a0 * t.dd);
+  t.on = Fr > 0.0f;
+  t.Fn = t.on ? Fr : 0.0f;
   // tangential spring with history, Coulomb cap
-  const float kt = bc.kappa_t * (2.0f * bc.eH - 1.0f) * kn * a0;
-  const float ct = bc.gn * kt;
-  const float3 vt = in.u - dd * in.n;
-  float3 xt = in.xt;
-  const float xn = dot(xt, in.n);
-  float3 xp = xt - xn * in.n;
-  const float lp2 = dot(xp, xp);
-  if (lp2 > 0.0f) xp = sqrtf(dot(xt, xt) / lp2) * xp;
-  xt = xp + bc.dt * vt;
-  float3 Ft = (-kt) * xt - ct * vt;
-  const float capt = in.mu_t * Fn;
-  const float Ft2 = dot(Ft, Ft);
-  if (Ft2 > capt * capt) {
-    Ft = (capt * rsqrtf(Ft2)) * Ft;
-    xt = (-1.0f / kt) * (Ft + ct * vt);
+  t.kt = bc.kappa_t * (2.0f * bc.eH - 1.0f) * t.kn * t.a0;
+  t.ct = bc.gn * t.kt;
+  t.vt = in.u - t.dd * in.n;
+  t.xn = dot(in.xt, in.n);
+  t.xp0 = in.xt - t.xn * in.n;
+  t.lp2 = dot(t.xp0, t.xp0);
+  t.rot = t.lp2 > 0.0f;
+  t.sc = t.rot ? sqrtf(dot(in.xt, in.xt) / t.lp2) : 1.0f;
+  const float3 xp = t.rot ? t.sc * t.xp0 : t.xp0;
+  t.xt1 = xp + bc.dt * t.vt;
+  t.Ftr = (-t.kt) * t.xt1 - t.ct * t.vt;
+  t.capt = in.mu_t * t.Fn;
+  t.Ft2 = dot(t.Ftr, t.Ftr);
+  t.slip = t.Ft2 > t.capt * t.capt;
+  if (t.slip) {
+    o.Ft = (t.capt * rsqrtf(t.Ft2)) * t.Ftr;
+    o.xt = (-1.0f / t.kt) * (o.Ft + t.ct * t.vt);
+  } else {
+    o.Ft = t.Ftr;
+    o.xt = t.xt1;
   }
   // rolling spring with history, rolling-resistance cap
-  const float kr = kt * rstar * rstar;
-  const float cr = bc.gn * kr;
-  float3 xr = in.xr + bc.dt * in.wrel;
-  float3 M = (-kr) * xr - cr * in.wrel;
-  const float capr = in.mu_r * rstar * Fn;
-  const float M2 = dot(M, M);
-  if (M2 > capr * capr) {
-    M = (capr * rsqrtf(M2)) * M;
-    xr = (-1.0f / kr) * (M + cr * in.wrel);
+  t.kr = t.kt * t.rstar * t.rstar;
+  t.cr = bc.gn * t.kr;
+  t.xr1 = in.xr + bc.dt * in.wrel;
+  t.Mtr = (-t.kr) * t.xr1 - t.cr * in.wrel;
+  t.capr = in.mu_r * t.rstar * t.Fn;
+  t.M2 = dot(t.Mtr, t.Mtr);
+  t.roll = t.M2 > t.capr * t.capr;
+  if (t.roll) {
+    o.M = (t.capr * rsqrtf(t.M2)) * t.Mtr;
+    o.xr = (-1.0f / t.kr) * (o.M + t.cr * in.wrel);
+  } else {
+    o.M = t.Mtr;
+    o.xr = t.xr1;
   }
-  o.F = Ft - Fn * in.n;
-  o.Ft = Ft;
-  o.M = M;
-  o.xt = xt;
-  o.xr = xr;
+  o.F = o.Ft - t.Fn * in.n;
+}
+
+__device__ __forceinline__ void contact_law(const BedConst& bc, const LawIn& in, LawOut& o) {
+  LawTape t;
+  law_forward(bc, in, t, o);
+}
+
+// Adjoints of the law's inputs.
+struct LawBar {
+  float delta;
+  float3 n, u, wrel, xt, xr;
+  float kn, mu_t, mu_r;
+};
+
+__device__ __forceinline__ float3 zero3() { return make_float3(0.f, 0.f, 0.f); }
+
+// Vector-Jacobian product of law_forward, the branches held as taped.
+// Fb, Ftb, Mb: adjoints of the outputs F, Ft, M; xtb, xrb: of the new springs.
+__device__ __forceinline__ void law_vjp(const BedConst& bc, const LawIn& in, const LawTape& t, const LawOut& o,
+                                        float3 Fb, float3 Ftb, float3 Mb, float3 xtb, float3 xrb, LawBar& r) {
+  // F = Ft - Fn n
+  Ftb = Ftb + Fb;
+  float Fnb = -dot(Fb, in.n);
+  float3 nb = (-t.Fn) * Fb;
+  float3 ub = zero3(), wb = zero3(), vtb = zero3(), xt1b = zero3(), xr1b = zero3(), Ftrb = zero3(), Mtrb = zero3();
+  float ktb = 0.f, ctb = 0.f, krb = 0.f, crb = 0.f, captb = 0.f, caprb = 0.f;
+  // rolling
+  if (t.roll) {
+    const float ikr = 1.0f / t.kr;
+    Mb = Mb - ikr * xrb;
+    crb += -dot(xrb, in.wrel) * ikr;
+    wb = wb + (-t.cr * ikr) * xrb;
+    krb += -dot(xrb, o.xr) * ikr;
+    const float Mn = sqrtf(t.M2);
+    const float3 m = (1.0f / Mn) * t.Mtr;
+    const float mb = dot(Mb, m);
+    caprb += mb;
+    Mtrb = Mtrb + (t.capr / Mn) * (Mb - mb * m);
+  } else {
+    xr1b = xr1b + xrb;
+    Mtrb = Mtrb + Mb;
+  }
+  krb += -dot(Mtrb, t.xr1);
+  xr1b = xr1b + (-t.kr) * Mtrb;
+  crb += -dot(Mtrb, in.wrel);
+  wb = wb + (-t.cr) * Mtrb;
+  r.xr = xr1b;
+  wb = wb + bc.dt * xr1b;
+  r.mu_r = caprb * t.rstar * t.Fn;
+  Fnb += caprb * in.mu_r * t.rstar;
+  krb += bc.gn * crb;
+  ktb += krb * t.rstar * t.rstar;
+  // tangential
+  if (t.slip) {
+    const float ikt = 1.0f / t.kt;
+    Ftb = Ftb - ikt * xtb;
+    ctb += -dot(xtb, t.vt) * ikt;
+    vtb = vtb + (-t.ct * ikt) * xtb;
+    ktb += -dot(xtb, o.xt) * ikt;
+    const float Fnrm = sqrtf(t.Ft2);
+    const float3 f = (1.0f / Fnrm) * t.Ftr;
+    const float fb = dot(Ftb, f);
+    captb += fb;
+    Ftrb = Ftrb + (t.capt / Fnrm) * (Ftb - fb * f);
+  } else {
+    xt1b = xt1b + xtb;
+    Ftrb = Ftrb + Ftb;
+  }
+  ktb += -dot(Ftrb, t.xt1);
+  xt1b = xt1b + (-t.kt) * Ftrb;
+  ctb += -dot(Ftrb, t.vt);
+  vtb = vtb + (-t.ct) * Ftrb;
+  r.mu_t = captb * t.Fn;
+  Fnb += captb * in.mu_t;
+  const float3 xpb = xt1b;
+  vtb = vtb + bc.dt * xt1b;
+  float3 xp0b, xob = zero3();
+  if (t.rot) {
+    xp0b = t.sc * xpb;
+    const float scb = dot(xpb, t.xp0);
+    const float lo2b = scb / (2.0f * t.sc * t.lp2);
+    const float lp2b = -scb * t.sc / (2.0f * t.lp2);
+    xp0b = xp0b + (2.0f * lp2b) * t.xp0;
+    xob = xob + (2.0f * lo2b) * in.xt;
+  } else {
+    xp0b = xpb;
+  }
+  xob = xob + xp0b;
+  const float xnb = -dot(xp0b, in.n);
+  nb = nb + (-t.xn) * xp0b;
+  xob = xob + xnb * in.n;
+  nb = nb + xnb * in.xt;
+  r.xt = xob;
+  // vt = u - dd n
+  ub = ub + vtb;
+  float ddb = -dot(vtb, in.n);
+  nb = nb + (-t.dd) * vtb;
+  ktb += bc.gn * ctb;
+  const float kfe = bc.kappa_t * (2.0f * bc.eH - 1.0f);
+  float knb = ktb * kfe * t.a0;
+  float a0b = ktb * kfe * t.kn;
+  // normal
+  const float Frb = t.on ? Fnb : 0.0f;
+  knb += Frb * (t.a1 + bc.eH * bc.gn * t.a0 * t.dd);
+  const float a1b = Frb * t.kn;
+  a0b += Frb * t.kn * bc.eH * bc.gn * t.dd;
+  ddb += Frb * t.kn * bc.eH * bc.gn * t.a0;
+  ub = ub + ddb * in.n;
+  nb = nb + ddb * in.u;
+  // a1 = delta^(2e-1), a0 = delta^(2e-2)
+  r.delta = (a1b * (2.0f * bc.eH - 1.0f) * t.a1 + a0b * (2.0f * bc.eH - 2.0f) * t.a0) / in.delta;
+  r.n = nb;
+  r.u = ub;
+  r.wrel = wb;
+  r.kn = knb;
 }
 
 __device__ __forceinline__ bool owner_rule(float ri, int si, float rj, int sj) {

@@ -62,6 +62,37 @@ struct DevBufs {
   uint32_t* stat;        // [0] max owner count at last rebuild, [1] rebuilds
 };
 
+// Adjoint work buffers: per-step records of one checkpoint segment (the
+// state, springs and wall poses each step read), the segment's fixed
+// candidate lists, the running adjoints and per-particle FP64 parameter
+// adjoints.
+struct AdjBufs {
+  double4* pos;          // [steps][N]
+  float4* vel;           // [steps][N]
+  float4* omg;           // [steps][N]
+  uint32_t* cflag;       // [steps][N]
+  float4* hA;            // [steps][K][N]
+  float2* hB;
+  float4* wA;            // [steps][nwall_max][N]
+  float2* wB;
+  WallPose* walls;       // [steps][nwall_total]
+  int32_t nwall_total, nwall_max;
+  int32_t* own_cnt;      // lists of the segment
+  int32_t* own_idx;
+  uint32_t* rev_start;
+  uint32_t* rev_ent;
+  float4* xb;            // adjoints of position, velocity, angular velocity
+  float4* vb;
+  float4* wb;
+  float4* Fb;            // adjoints of the accumulated force and torque
+  float4* Tb;
+  float4* hbA[2];        // spring adjoints by owner slot (ping-pong)
+  float2* hbB[2];
+  float4* wbA[2];        // wall spring adjoints
+  float2* wbB[2];
+  double* theta;         // [N][3] adjoints of (s_k, mu_t, mu_r)
+};
+
 // Parities of one step, known on the host.
 struct StepPar {
   int s;     // state buffer read this step
@@ -85,5 +116,10 @@ int step_occupancy(int block);
 void launch_advance(const DevBufs& d, int block, hipStream_t st);
 void launch_poses(const DevBufs& d, hipStream_t st);
 size_t scan_tmp_elems(int64_t n);
+void launch_adj_pre(const DevBufs& d, const AdjBufs& a, int q, hipStream_t st);
+void launch_adj_step(const DevBufs& d, const AdjBufs& a, int q, int hp, int obj_body, float invT, hipStream_t st);
+void launch_adj_remap(const DevBufs& d, const AdjBufs& a, const int32_t* old_cnt, const int32_t* old_idx,
+                      const uint32_t* old_flag, int hp, hipStream_t st);
+void launch_adj_theta(const DevBufs& d, const AdjBufs& a, double* out3, hipStream_t st);
 
 }  // namespace lpr

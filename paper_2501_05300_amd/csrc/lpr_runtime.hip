@@ -44,6 +44,9 @@ struct HostBed {
   int nwall = 0, nbody = 0, nlev = 0;
   int wall0 = 0, body0 = 0, lev0 = 0;
   double dt = 0.0;
+  double rmin = 0.0;
+  lpr_params params{};
+  std::vector<lpr_body> bodies;
 };
 
 uint64_t spread3(uint64_t v) {  // 21 bits -> every third bit
@@ -122,6 +125,20 @@ struct lpr_bed {
   int max_walls = 0;
   bool faulted = false;
   lpr_status fault_status = LPR_OK;
+  // adjoint storage (allocated on first use, grown as needed)
+  AdjBufs adj{};
+  int adj_steps = 0;      // per-step records available
+  int adj_ckpts = 0;      // checkpoints available
+  struct Ckpt {
+    double4* pos; float4* vel; float4* omg;
+    uint32_t* cflag; float4* hA; float2* hB; float4* wA; float2* wB;
+    int32_t* own_cnt; int32_t* own_idx;
+    BedDyn* bedyn; BodyDyn* bdyn;
+    int s, h, l;
+    int64_t since, host_steps, rebuilds;
+  };
+  std::vector<Ckpt> ckpts;
+  double* theta_out = nullptr;
 
   void* dalloc(size_t bytes) {
     bytes = (bytes + 255) & ~(size_t)255;
@@ -480,6 +497,10 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
     body_total += H.nbody;
     max_walls = std::max(max_walls, H.nwall);
     H.dt = D->params.dt;
+    H.params = D->params;
+    H.bodies.assign(D->bodies, D->bodies + D->n_bodies);
+    H.rmin = std::numeric_limits<double>::max();
+    for (int64_t i = 0; i < D->n; ++i) H.rmin = std::min(H.rmin, (double)D->radius[i]);
   }
   if (cell_base >= (int64_t(1) << 31) - 2) {
     delete b;
@@ -573,6 +594,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
     }
     const double Estar = 1.0 / ((1.0 - P.nu * P.nu) / P.E + (1.0 - P.nu * P.nu) / P.E);
     C.kfac = (float)(P.s_k * Estar / 3.0);
+    C.s_k = (float)P.s_k;
     C.gn = (float)(P.gamma_factor * P.dt);
     C.eH = (float)P.e_H;
     C.kappa_t = (float)P.kappa_t;
@@ -1210,6 +1232,259 @@ lpr_status lpr_autotune(const lpr_bed_desc* const* descs, int32_t n_beds, const 
   if (n_trials) *n_trials = (int32_t)done.size();
   if (trials)
     for (int q = 0; q < (int)done.size() && q < capacity; ++q) trials[q] = done[q];
+  return LPR_OK;
+}
+
+namespace {
+
+bool adj_reserve(lpr_bed* b, int steps, int nckpt) {
+  DevBufs& d = b->d;
+  const int64_t N = d.N;
+  const int W = b->max_walls;
+  AdjBufs& a = b->adj;
+  if (b->adj_steps < steps) {
+    bool ok = dal(b, &a.pos, (size_t)steps * N) && dal(b, &a.vel, (size_t)steps * N) &&
+              dal(b, &a.omg, (size_t)steps * N) && dal(b, &a.cflag, (size_t)steps * N) &&
+              dal(b, &a.hA, (size_t)steps * K * N) && dal(b, &a.hB, (size_t)steps * K * N) &&
+              dal(b, &a.wA, (size_t)steps * W * N) && dal(b, &a.wB, (size_t)steps * W * N);
+    const int nw = std::max(1, (int)(b->hb.back().wall0 + b->hb.back().nwall));
+    ok = ok && dal(b, &a.walls, (size_t)steps * nw);
+    if (!ok) return false;
+    a.nwall_total = nw;
+    a.nwall_max = W;
+    b->adj_steps = steps;
+  }
+  if (!a.xb) {
+    bool ok = dal(b, &a.own_cnt, N) && dal(b, &a.own_idx, (size_t)K * N) && dal(b, &a.rev_start, N + 1) &&
+              dal(b, &a.rev_ent, (size_t)K * N) && dal(b, &a.xb, N) && dal(b, &a.vb, N) && dal(b, &a.wb, N) &&
+              dal(b, &a.Fb, N) && dal(b, &a.Tb, N) && dal(b, &a.theta, 3 * N) && dal(b, &b->theta_out, 3);
+    for (int q = 0; q < 2; ++q)
+      ok = ok && dal(b, &a.hbA[q], (size_t)K * N) && dal(b, &a.hbB[q], (size_t)K * N) &&
+           dal(b, &a.wbA[q], (size_t)W * N) && dal(b, &a.wbB[q], (size_t)W * N);
+    if (!ok) return false;
+  }
+  while ((int)b->ckpts.size() < nckpt) {
+    lpr_bed::Ckpt c{};
+    const size_t nb = std::max<size_t>(1, b->hb.back().body0 + b->hb.back().nbody);
+    bool ok = dal(b, &c.pos, N) && dal(b, &c.vel, N) && dal(b, &c.omg, N) && dal(b, &c.cflag, N) &&
+              dal(b, &c.hA, (size_t)K * N) && dal(b, &c.hB, (size_t)K * N) && dal(b, &c.wA, (size_t)W * N) &&
+              dal(b, &c.wB, (size_t)W * N) && dal(b, &c.own_cnt, N) && dal(b, &c.own_idx, (size_t)K * N) &&
+              dal(b, &c.bedyn, b->hb.size()) && dal(b, &c.bdyn, nb);
+    if (!ok) return false;
+    b->ckpts.push_back(c);
+  }
+  return true;
+}
+
+hipError_t d2d(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
+}
+
+lpr_status ckpt_save(lpr_bed* b, lpr_bed::Ckpt& c) {
+  DevBufs& d = b->d;
+  const int64_t N = d.N;
+  const int W = b->max_walls;
+  const size_t nb = std::max<size_t>(1, b->hb.back().body0 + b->hb.back().nbody);
+  hipStream_t st = b->stream;
+  HIPTRY(d2d(c.pos, d.pos[b->s], sizeof(double4) * N, st));
+  HIPTRY(d2d(c.vel, d.vel[b->s], sizeof(float4) * N, st));
+  HIPTRY(d2d(c.omg, d.omg[b->s], sizeof(float4) * N, st));
+  HIPTRY(d2d(c.cflag, d.cflag[b->h], sizeof(uint32_t) * N, st));
+  HIPTRY(d2d(c.hA, d.hA[b->h], sizeof(float4) * K * N, st));
+  HIPTRY(d2d(c.hB, d.hB[b->h], sizeof(float2) * K * N, st));
+  HIPTRY(d2d(c.wA, d.wA[b->h], sizeof(float4) * W * N, st));
+  HIPTRY(d2d(c.wB, d.wB[b->h], sizeof(float2) * W * N, st));
+  HIPTRY(d2d(c.own_cnt, d.own_cnt[b->l], sizeof(int32_t) * N, st));
+  HIPTRY(d2d(c.own_idx, d.own_idx[b->l], sizeof(int32_t) * K * N, st));
+  HIPTRY(d2d(c.bedyn, d.bedyn, sizeof(BedDyn) * b->hb.size(), st));
+  HIPTRY(d2d(c.bdyn, d.bdyn, sizeof(BodyDyn) * nb, st));
+  c.s = b->s; c.h = b->h; c.l = b->l;
+  c.since = b->since; c.host_steps = b->host_steps; c.rebuilds = b->rebuilds;
+  return LPR_OK;
+}
+
+lpr_status ckpt_restore(lpr_bed* b, const lpr_bed::Ckpt& c) {
+  DevBufs& d = b->d;
+  const int64_t N = d.N;
+  const int W = b->max_walls;
+  const size_t nb = std::max<size_t>(1, b->hb.back().body0 + b->hb.back().nbody);
+  hipStream_t st = b->stream;
+  b->s = c.s; b->h = c.h; b->l = c.l;
+  b->since = c.since; b->host_steps = c.host_steps; b->rebuilds = c.rebuilds;
+  HIPTRY(d2d(d.pos[b->s], c.pos, sizeof(double4) * N, st));
+  HIPTRY(d2d(d.vel[b->s], c.vel, sizeof(float4) * N, st));
+  HIPTRY(d2d(d.omg[b->s], c.omg, sizeof(float4) * N, st));
+  HIPTRY(d2d(d.cflag[b->h], c.cflag, sizeof(uint32_t) * N, st));
+  HIPTRY(d2d(d.hA[b->h], c.hA, sizeof(float4) * K * N, st));
+  HIPTRY(d2d(d.hB[b->h], c.hB, sizeof(float2) * K * N, st));
+  HIPTRY(d2d(d.wA[b->h], c.wA, sizeof(float4) * W * N, st));
+  HIPTRY(d2d(d.wB[b->h], c.wB, sizeof(float2) * W * N, st));
+  HIPTRY(d2d(d.own_cnt[b->l], c.own_cnt, sizeof(int32_t) * N, st));
+  HIPTRY(d2d(d.own_idx[b->l], c.own_idx, sizeof(int32_t) * K * N, st));
+  HIPTRY(d2d(d.bedyn, c.bedyn, sizeof(BedDyn) * b->hb.size(), st));
+  HIPTRY(d2d(d.bdyn, c.bdyn, sizeof(BodyDyn) * nb, st));
+  launch_poses(d, st);
+  return LPR_OK;
+}
+
+lpr_status set_device_skin(lpr_bed* b, float skin) {
+  for (size_t q = 0; q < b->hb.size(); ++q)
+    HIPTRY(hipMemcpy((char*)(b->d.beds + q) + offsetof(BedConst, skin), &skin, sizeof(float), hipMemcpyHostToDevice));
+  return LPR_OK;
+}
+
+}  // namespace
+
+lpr_status lpr_set_contact_params(lpr_bed* b, double s_k, double mu_t, double mu_r) {
+  lpr_status g = guard(b);
+  if (g != LPR_OK) return g;
+  if (!(s_k > 0.0) || !(mu_t >= 0.0) || !(mu_r >= 0.0)) return fail(LPR_E_INVAL, "invalid contact parameters");
+  HIPTRY(hipStreamSynchronize(b->stream));
+  for (size_t q = 0; q < b->hb.size(); ++q) {
+    HostBed& H = b->hb[q];
+    H.params.s_k = s_k;
+    H.params.mu_t = mu_t;
+    H.params.mu_r = mu_r;
+    const lpr_params& P = H.params;
+    BedConst C;
+    HIPTRY(hipMemcpy(&C, b->d.beds + q, sizeof(BedConst), hipMemcpyDeviceToHost));
+    const double Estar = 1.0 / ((1.0 - P.nu * P.nu) / P.E + (1.0 - P.nu * P.nu) / P.E);
+    C.kfac = (float)(P.s_k * Estar / 3.0);
+    C.s_k = (float)P.s_k;
+    C.mu_t = (float)P.mu_t;
+    C.mu_r = (float)P.mu_r;
+    HIPTRY(hipMemcpy(b->d.beds + q, &C, sizeof(BedConst), hipMemcpyHostToDevice));
+  }
+  return LPR_OK;
+}
+
+lpr_status lpr_adjoint_window(lpr_bed* b, int64_t n_steps, int32_t ckpt_every, int32_t body, double* J_out,
+                              double grad_out[3]) {
+  lpr_status g = guard(b);
+  if (g != LPR_OK) return g;
+  if (b->hb.size() != 1) return fail(LPR_E_INVAL, "the adjoint window runs on a single bed");
+  const HostBed& H = b->hb[0];
+  if (n_steps <= 0 || ckpt_every <= 0 || !J_out || !grad_out) return fail(LPR_E_INVAL, "bad arguments");
+  if (body < 0 || body >= H.nbody) return fail(LPR_E_INVAL, "body out of range");
+  for (const lpr_body& B : H.bodies)
+    if (B.z_free || B.ang_vel != 0.0)
+      return fail(LPR_E_INVAL, "the adjoint supports prescribed, non-rotating bodies only");
+  lpr_status st = sync_check(b);
+  if (st != LPR_OK) return st;
+  DevBufs& d = b->d;
+  const int64_t N = d.N;
+  const int C = (int)std::min<int64_t>(ckpt_every, n_steps);
+  const int64_t nseg = (n_steps + C - 1) / C;
+  if (!adj_reserve(b, C, (int)nseg + 1)) return fail(LPR_E_NOMEM, "adjoint buffers");
+  // candidate lists fixed within a segment: rebuilt at each segment start
+  // with a skin that must hold for the whole segment
+  const int R0 = b->R, Reff0 = b->R_eff;
+  const float skin0 = b->skin;
+  const float skin = std::max(skin0, (float)(0.25 * H.rmin));
+  b->R = C;
+  b->R_eff = C;
+  b->skin = skin;
+  if ((st = set_device_skin(b, C > 1 ? skin : 0.f)) != LPR_OK) return st;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->has_graph = false;
+  auto restore_mode = [&]() {
+    b->R = R0;
+    b->R_eff = Reff0;
+    b->skin = skin0;
+    (void)set_device_skin(b, skin0);
+  };
+  double sum6[6];
+  int64_t wsteps = 0;
+  if ((st = reaction_window_impl(b, 0, body, sum6, &wsteps, 1)) != LPR_OK) { restore_mode(); return st; }
+  const int64_t trips0 = b->skin_trips;
+  // forward window with checkpoints
+  for (int64_t s = 0; s < nseg; ++s) {
+    if ((st = ckpt_save(b, b->ckpts[s])) != LPR_OK) { restore_mode(); return st; }
+    b->since = std::numeric_limits<int64_t>::max() / 2;
+    const int64_t ns = std::min<int64_t>(C, n_steps - s * C);
+    for (int64_t q = 0; q < ns; ++q) enqueue_step(b);
+  }
+  if ((st = sync_check(b)) != LPR_OK) { restore_mode(); return st; }
+  if (b->skin_trips != trips0) {
+    restore_mode();
+    return fail(LPR_E_STATE, "a particle moved more than the skin within a checkpoint segment; "
+                             "use a shorter checkpoint interval");
+  }
+  if ((st = reaction_window_impl(b, 0, body, sum6, &wsteps, 1)) != LPR_OK) { restore_mode(); return st; }
+  const double J = sum6[2] / (double)n_steps;
+  lpr_bed::Ckpt& end = b->ckpts[nseg];
+  if ((st = ckpt_save(b, end)) != LPR_OK) { restore_mode(); return st; }
+  // reverse sweep
+  AdjBufs& a = b->adj;
+  hipStream_t sm = b->stream;
+  const int W = b->max_walls;
+  HIPTRY(hipMemsetAsync(a.xb, 0, sizeof(float4) * N, sm));
+  HIPTRY(hipMemsetAsync(a.vb, 0, sizeof(float4) * N, sm));
+  HIPTRY(hipMemsetAsync(a.wb, 0, sizeof(float4) * N, sm));
+  HIPTRY(hipMemsetAsync(a.theta, 0, sizeof(double) * 3 * N, sm));
+  for (int q = 0; q < 2; ++q) {
+    HIPTRY(hipMemsetAsync(a.hbA[q], 0, sizeof(float4) * K * N, sm));
+    HIPTRY(hipMemsetAsync(a.hbB[q], 0, sizeof(float2) * K * N, sm));
+    HIPTRY(hipMemsetAsync(a.wbA[q], 0, sizeof(float4) * W * N, sm));
+    HIPTRY(hipMemsetAsync(a.wbB[q], 0, sizeof(float2) * W * N, sm));
+  }
+  const int obj = H.body0 + body;
+  const float invT = (float)(1.0 / (double)n_steps);
+  int hp = 0;
+  for (int64_t s = nseg - 1; s >= 0; --s) {
+    const lpr_bed::Ckpt& ck = b->ckpts[s];
+    if ((st = ckpt_restore(b, ck)) != LPR_OK) { restore_mode(); return st; }
+    b->since = std::numeric_limits<int64_t>::max() / 2;
+    const int ns = (int)std::min<int64_t>(C, n_steps - s * C);
+    for (int q = 0; q < ns; ++q) {  // recompute, recording each step's inputs
+      if (b->since >= b->R_eff) enqueue_rebuild(b);
+      if (q == 0) {
+        HIPTRY(d2d(a.own_cnt, d.own_cnt[b->l], sizeof(int32_t) * N, sm));
+        HIPTRY(d2d(a.own_idx, d.own_idx[b->l], sizeof(int32_t) * K * N, sm));
+        HIPTRY(d2d(a.rev_start, d.rev_start, sizeof(uint32_t) * (N + 1), sm));
+        HIPTRY(d2d(a.rev_ent, d.rev_ent, sizeof(uint32_t) * K * N, sm));
+      }
+      HIPTRY(d2d(a.pos + (int64_t)q * N, d.pos[b->s], sizeof(double4) * N, sm));
+      HIPTRY(d2d(a.vel + (int64_t)q * N, d.vel[b->s], sizeof(float4) * N, sm));
+      HIPTRY(d2d(a.omg + (int64_t)q * N, d.omg[b->s], sizeof(float4) * N, sm));
+      HIPTRY(d2d(a.cflag + (int64_t)q * N, d.cflag[b->h], sizeof(uint32_t) * N, sm));
+      HIPTRY(d2d(a.hA + (int64_t)q * K * N, d.hA[b->h], sizeof(float4) * K * N, sm));
+      HIPTRY(d2d(a.hB + (int64_t)q * K * N, d.hB[b->h], sizeof(float2) * K * N, sm));
+      HIPTRY(d2d(a.wA + (int64_t)q * W * N, d.wA[b->h], sizeof(float4) * W * N, sm));
+      HIPTRY(d2d(a.wB + (int64_t)q * W * N, d.wB[b->h], sizeof(float2) * W * N, sm));
+      HIPTRY(d2d(a.walls + (int64_t)q * a.nwall_total, d.walls, sizeof(WallPose) * a.nwall_total, sm));
+      StepPar p{b->s, b->h, b->l, false};
+      launch_step(d, p, b->block, b->record, b->persist_blocks, sm);
+      launch_advance(d, b->block, sm);
+      b->s ^= 1;
+      b->h ^= 1;
+      b->since += 1;
+      b->host_steps += 1;
+    }
+    for (int q = ns - 1; q >= 0; --q) {
+      launch_adj_pre(d, a, q, sm);
+      launch_adj_step(d, a, q, hp, obj, invT, sm);
+      hp ^= 1;
+    }
+    if (s > 0) {
+      launch_adj_remap(d, a, ck.own_cnt, ck.own_idx, ck.cflag, hp, sm);
+      hp ^= 1;
+    }
+    HIPTRY(hipGetLastError());
+  }
+  launch_adj_theta(d, a, b->theta_out, sm);
+  double grad[3];
+  HIPTRY(hipMemcpyAsync(grad, b->theta_out, sizeof(grad), hipMemcpyDeviceToHost, sm));
+  HIPTRY(hipStreamSynchronize(sm));
+  // back to the state after the window
+  if ((st = ckpt_restore(b, end)) != LPR_OK) { restore_mode(); return st; }
+  restore_mode();
+  if ((st = sync_check(b)) != LPR_OK) return st;
+  *J_out = J;
+  for (int c = 0; c < 3; ++c) grad_out[c] = grad[c];
   return LPR_OK;
 }
 

@@ -28,7 +28,7 @@ _PER_BED = ("get_state", "set_state", "get_history", "set_history", "read_contac
             "reaction_window", "read_body", "set_clock", "get_clock", "set_body_state")
 SYMBOLS = ("lpr_bed_create", "lpr_bed_destroy", "lpr_step", "lpr_step_profiled", "lpr_sync", "lpr_get_stats",
            "lpr_status_str", "lpr_last_error", "lpr_batch_create", "lpr_batch_size", "lpr_set_launch",
-           "lpr_autotune") + tuple("lpr_" + f for f in _PER_BED) + tuple("lpr_batch_" + f for f in _PER_BED)
+           "lpr_autotune", "lpr_set_contact_params", "lpr_adjoint_window") + tuple("lpr_" + f for f in _PER_BED) + tuple("lpr_batch_" + f for f in _PER_BED)
 
 
 class LprError(RuntimeError):
@@ -133,6 +133,8 @@ def load_library(path: str = LIB_PATH):
                                ctypes.POINTER(vp)]
     sig["lpr_batch_size"] = [vp, ctypes.POINTER(i32)]
     sig["lpr_set_launch"] = [vp, i32, i32]
+    sig["lpr_set_contact_params"] = [vp, d, d, d]
+    sig["lpr_adjoint_window"] = [vp, i64, i32, i32, ctypes.POINTER(d), vp]
     sig["lpr_autotune"] = [ctypes.POINTER(ctypes.POINTER(_Desc)), i32, ctypes.POINTER(_Allocator), vp, i32,
                            ctypes.POINTER(_Tuning), ctypes.POINTER(_Tuning), i32, ctypes.POINTER(i32)]
     for name, args in sig.items():
@@ -285,6 +287,17 @@ class _Stepper:
 
     def set_launch(self, block, persistent=False):
         _check(_lib.lpr_set_launch(self._h, int(block), 1 if persistent else 0), "lpr_set_launch")
+
+    def set_contact_params(self, s_k, mu_t, mu_r):
+        _check(_lib.lpr_set_contact_params(self._h, float(s_k), float(mu_t), float(mu_r)), "lpr_set_contact_params")
+
+    def adjoint_window(self, n_steps, ckpt_every, body):
+        """J = mean z reaction on `body` over n_steps and dJ/d(s_k, mu_t, mu_r)."""
+        J = ctypes.c_double(0.0)
+        g = np.zeros(3)
+        _check(_lib.lpr_adjoint_window(self._h, int(n_steps), int(ckpt_every), int(body), ctypes.byref(J), _ptr(g)),
+               "lpr_adjoint_window")
+        return J.value, g
 
     def stats(self):
         s = _Stats()
@@ -465,3 +478,30 @@ def autotune(specs, trial_steps=20, rebuild_every=1, skin=0.0, device=0):
     _check(rc, "lpr_autotune")
     as_dict = lambda t: {f: getattr(t, f) for f, _ in _Tuning._fields_}
     return as_dict(best), [as_dict(trials[q]) for q in range(nt.value)]
+
+
+def plate_reaction_window():
+    """torch.autograd.Function: J(theta) = mean plate reaction over a window
+    of steps from a bed's current state, theta = (s_k, mu_t, mu_r).
+
+    forward(theta, bed, n_steps, ckpt_every, body) sets the bed's contact
+    parameters to theta and runs lpr_adjoint_window, which steps the window
+    and computes dJ/dtheta by the hand-written adjoint; backward scales that
+    gradient by the incoming one.  The bed advances by the window."""
+    import torch
+
+    class PlateReactionWindow(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, theta, bed, n_steps, ckpt_every, body):
+            th = theta.detach().double().cpu().numpy()
+            bed.set_contact_params(th[0], th[1], th[2])
+            J, g = bed.adjoint_window(n_steps, ckpt_every, body)
+            ctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype, device=theta.device))
+            return torch.as_tensor(J, dtype=theta.dtype, device=theta.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (g,) = ctx.saved_tensors
+            return grad_out * g, None, None, None, None
+
+    return PlateReactionWindow

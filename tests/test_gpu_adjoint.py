@@ -1,0 +1,95 @@
+"""Adjoint form: dJ/d(s_k, mu_t, mu_r) of the mean plate reaction (GPU)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2501_05300_amd import beds
+from parity_util import oracle_from_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def pressed_bed(seed=0, speed=1.0, pre=600):
+    """Two-layer bed (2,000 spheres) under a full-width plate pushed down;
+    returns the spec and a GPU bed advanced `pre` steps so that the plate is
+    in contact."""
+    from paper_2501_05300_amd.lprdem import Bed
+    spec = beds.add_plate(beds.two_layer_bed(seed), speed=speed, full_width=True)
+    bed = Bed(spec)
+    bed.step(pre)
+    return spec, bed
+
+
+def test_adjoint_matches_oracle_fp64_gradient():
+    spec, bed = pressed_bed()
+    ob = oracle_from_gpu(spec, bed)
+    T = 300
+    J, g = bed.adjoint_window(T, 100, 1)
+    Jo, go = ob.tangent_window(T, 1, 2)
+    print("gpu", J, g, "oracle", Jo, go)
+    assert abs(Jo) > 1e-3
+    assert abs(J - Jo) <= 1e-4 * abs(Jo)
+    scale = np.abs(go) + 1e-3 * abs(Jo) / np.array([1.0, 0.4, 0.02])
+    assert np.all(np.abs(g - go) <= 1e-3 * scale), (g, go)
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    res = []
+    for ck in (25, 100, 200):
+        spec, bed = pressed_bed(seed=1)
+        res.append(bed.adjoint_window(200, ck, 1))
+    for J, g in res[1:]:
+        assert J == res[0][0]
+        np.testing.assert_allclose(g, res[0][1], rtol=1e-6, atol=0)
+
+
+def test_adjoint_leaves_the_bed_where_the_forward_window_ends():
+    spec, a = pressed_bed(seed=2)
+    _, b = pressed_bed(seed=2)
+    a.adjoint_window(150, 50, 1)
+    b.step(150)
+    xa, va, _ = a.state()
+    xb, vb, _ = b.state()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+
+
+def test_adjoint_matches_gpu_central_differences():
+    spec, bed0 = pressed_bed(seed=3)
+    x, v, w = bed0.state()
+    keys, vals = bed0.history()
+    clock = bed0.clock()
+    T = 200
+    J, g = bed0.adjoint_window(T, 100, 1)
+    from paper_2501_05300_amd.lprdem import Bed
+    names = ("s_k", "mu_t", "mu_r")
+    for q, name in enumerate(names):
+        p0 = getattr(spec.params, name)
+        h = 1e-4 * p0
+        acc = []
+        for sgn in (1, -1):
+            s2 = spec.copy()
+            s2.params = spec.params.replace(**{name: p0 + sgn * h})
+            b = Bed(s2)
+            b.set_state(x, v, w)
+            b.set_history(keys, vals)
+            b.set_clock(clock)
+            b.reaction_window(1, reset=True)
+            b.step(T)
+            sm, k = b.reaction_window(1)
+            acc.append(sm[2] / k)
+            b.close()
+        fd = (acc[0] - acc[1]) / (2 * h)
+        print(name, g[q], fd)
+        assert abs(g[q] - fd) <= 2e-2 * max(abs(fd), 1e-3 * abs(J) / p0), (name, g[q], fd)
+
+
+def test_autograd_function():
+    import torch
+    from paper_2501_05300_amd.lprdem import plate_reaction_window
+    spec, bed = pressed_bed(seed=4)
+    F = plate_reaction_window()
+    theta = torch.tensor([1.0, 0.4, 0.02], dtype=torch.float64, requires_grad=True)
+    J = F.apply(theta, bed, 100, 50, 1)
+    (gt,) = torch.autograd.grad(J, theta)
+    assert torch.isfinite(gt).all() and float(gt.abs().sum()) > 0
+    assert float(J) > 0
