@@ -224,6 +224,8 @@ typedef struct {
   int32_t max_owner_slots;  /* largest per-owner candidate count seen */
   int64_t skin_trips;       /* times a skin was exceeded between rebuilds
                                (those steps were rebuilt and repeated) */
+  int32_t adjoint_interval; /* checkpoint interval of the last adjoint window
+                               (0 before the first) */
 } lpr_stats;
 lpr_status lpr_get_stats(lpr_bed* bed, lpr_stats* out);
 
@@ -288,9 +290,14 @@ lpr_status lpr_autotune(const lpr_bed_desc* const* descs, int32_t n_beds, const 
  * lpr_adjoint_window steps a single bed n_steps steps from its current
  * state and returns J = (1/n_steps) sum_k R_z(k), the mean z reaction on
  * `body`, and dJ/d(s_k, mu_t, mu_r) by reverse mode: the window runs forward
- * with a checkpoint every ckpt_every steps (candidate lists rebuilt at each
- * checkpoint with a skin of max(skin, r_min/4) that must hold for the
- * segment; otherwise LPR_E_STATE); then, segment by segment in reverse, the
+ * with a checkpoint every ckpt_every steps.  Candidate lists are rebuilt at
+ * each checkpoint and kept for its segment, with the bed's skin or, for a
+ * bed without one, min(r_min/4, what its cell plan covers); a bed with
+ * neither (rebuild_every 1 and cell_factor 1) gives LPR_E_INVAL.  If a
+ * particle moves more than skin/2 within a segment, the forward restarts
+ * from the window start with half the interval (one-step segments rebuild
+ * every step and cannot trip); lpr_stats.adjoint_interval reports the
+ * interval used.  Then, segment by segment in reverse, the
  * checkpoint is restored, the segment recomputed with its per-step inputs
  * recorded, and the hand-written vector-Jacobian products of integration,
  * accumulation, contact law and geometry run step by step, holding the

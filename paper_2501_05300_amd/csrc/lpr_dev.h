@@ -13,7 +13,8 @@
 //   wA[2][W][N], wB[2][W][N]  the same for walls, indexed by wall
 //   cflag[2][N] uint32 bit k: owner slot k in contact; bit 16+w: wall w
 //   rev_start[N+1], rev_ent[*]  reverse (partner-side) entries, packed
-//                              owner << 4 | slot, ascending per partner
+//                              owner << 4 | slot, per partner in ascending
+//                              owner stable id
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -9,7 +9,7 @@
 //               every coarser level, 27 cells each; sorted by partner id;
 //               history carried over from the previous lists; reverse counts
 //   scan        reverse ranges;  k_rev_scatter / k_rev_sort: partner-side
-//               entries in a fixed order
+//               entries in ascending owner stable id
 // then every step:
 //   k_step      fused narrow phase + contact law + accumulation + walls +
 //               integration; each particle evaluates all of its contacts
@@ -350,18 +350,25 @@ void launch_rev_scatter(const DevBufs& d, int l, hipStream_t st) {
   hipLaunchKernelGGL(k_rev_scatter, dim3((unsigned)((d.N + 255) / 256)), dim3(256), 0, st, d, l);
 }
 
+// Partner-side entries of a particle in ascending stable id of the owner, so
+// that the order in which its forces are summed does not depend on the
+// storage order (and so on the cell layout); an owner holds a given partner
+// in one slot at most, so the keys are distinct.
 __global__ void k_rev_sort(DevBufs d) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= d.N || latched(d.err)) return;
   const uint32_t a = d.rev_start[j], b = d.rev_start[j + 1];
   for (uint32_t q = a + 1; q < b; ++q) {
-    const uint32_t key = d.rev_ent[q];
+    const uint32_t e = d.rev_ent[q];
+    const int32_t key = d.sid[e >> 4];
     uint32_t p = q;
-    while (p > a && d.rev_ent[p - 1] > key) {
-      d.rev_ent[p] = d.rev_ent[p - 1];
+    while (p > a) {
+      const uint32_t prev = d.rev_ent[p - 1];
+      if (d.sid[prev >> 4] <= key) break;
+      d.rev_ent[p] = prev;
       --p;
     }
-    d.rev_ent[p] = key;
+    d.rev_ent[p] = e;
   }
 }
 

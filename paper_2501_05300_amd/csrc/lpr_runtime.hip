@@ -45,6 +45,9 @@ struct HostBed {
   int wall0 = 0, body0 = 0, lev0 = 0;
   double dt = 0.0;
   double rmin = 0.0;
+  // largest skin the cell plan covers: one-cell stencils find every pair
+  // closer than r_i + r_j + skin_cap at the time the lists are built
+  double skin_cap = 0.0;
   lpr_params params{};
   std::vector<lpr_body> bodies;
 };
@@ -129,6 +132,7 @@ struct lpr_bed {
   AdjBufs adj{};
   int adj_steps = 0;      // per-step records available
   int adj_ckpts = 0;      // checkpoints available
+  int adj_interval = 0;   // checkpoint interval the last adjoint window used
   struct Ckpt {
     double4* pos; float4* vel; float4* omg;
     uint32_t* cflag; float4* hA; float2* hB; float4* wA; float2* wB;
@@ -240,6 +244,7 @@ void plan_bed(const lpr_bed_desc* D, double band_ratio, double cell_factor, doub
   }
   H.lev0 = (int)levels.size();
   H.nlev = nlev;
+  H.skin_cap = std::numeric_limits<double>::max();
   for (int q = 0; q < nlev; ++q) {
     LevelGrid G{};
     double rm = rmax[q] > 0.0 ? rmax[q] : thr[q + 1];
@@ -263,6 +268,13 @@ void plan_bed(const lpr_bed_desc* D, double band_ratio, double cell_factor, doub
         G.inv_w[a] = 1.0 / hcell;
         G.per[a] = 0;
       }
+    }
+    if (rmax[q] > 0.0) {
+      // the widest pair of this level (both radii at rm) is the one that
+      // needs the most room; pairs with a finer particle need less
+      double w = hcell;
+      for (int a = 0; a < 3; ++a) w = std::min(w, 1.0 / G.inv_w[a]);
+      H.skin_cap = std::min(H.skin_cap, w - 2.0 * rm);
     }
     G.base = cell_base;
     cell_base += (int64_t)G.n[0] * G.n[1] * G.n[2];
@@ -1109,6 +1121,7 @@ lpr_status lpr_get_stats(lpr_bed* b, lpr_stats* out) {
   out->cells = b->ncells;
   out->max_owner_slots = (int32_t)stat[0];
   out->skin_trips = b->skin_trips;
+  out->adjoint_interval = b->adj_interval;
   return LPR_OK;
 }
 
@@ -1373,18 +1386,17 @@ lpr_status lpr_adjoint_window(lpr_bed* b, int64_t n_steps, int32_t ckpt_every, i
   if (st != LPR_OK) return st;
   DevBufs& d = b->d;
   const int64_t N = d.N;
-  const int C = (int)std::min<int64_t>(ckpt_every, n_steps);
-  const int64_t nseg = (n_steps + C - 1) / C;
-  if (!adj_reserve(b, C, (int)nseg + 1)) return fail(LPR_E_NOMEM, "adjoint buffers");
-  // candidate lists fixed within a segment: rebuilt at each segment start
-  // with a skin that must hold for the whole segment
+  // Candidate lists stay fixed within a checkpoint segment: they are built
+  // at each segment start with a skin that has to cover the whole segment.
+  // The bed's own skin if it has one (its cells were planned for it), else a
+  // quarter of the smallest radius, never more than the cell plan covers.
+  const double skin_d = b->skin > 0.f ? (double)b->skin : std::min(0.25 * H.rmin, 0.9 * H.skin_cap);
+  if (!(skin_d > 0.0))
+    return fail(LPR_E_INVAL, "the adjoint window needs candidate lists with a skin: create the bed with "
+                             "rebuild_every > 1 and skin > 0, or with cell_factor > 1");
+  const float skin = (float)skin_d;
   const int R0 = b->R, Reff0 = b->R_eff;
   const float skin0 = b->skin;
-  const float skin = std::max(skin0, (float)(0.25 * H.rmin));
-  b->R = C;
-  b->R_eff = C;
-  b->skin = skin;
-  if ((st = set_device_skin(b, C > 1 ? skin : 0.f)) != LPR_OK) return st;
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->gexec = nullptr;
@@ -1395,24 +1407,43 @@ lpr_status lpr_adjoint_window(lpr_bed* b, int64_t n_steps, int32_t ckpt_every, i
     b->R_eff = Reff0;
     b->skin = skin0;
     (void)set_device_skin(b, skin0);
+    // the displacement record belongs to the recomputed segments: rebuild
+    // before the next step
+    b->since = std::numeric_limits<int64_t>::max() / 2;
   };
   double sum6[6];
   int64_t wsteps = 0;
   if ((st = reaction_window_impl(b, 0, body, sum6, &wsteps, 1)) != LPR_OK) { restore_mode(); return st; }
-  const int64_t trips0 = b->skin_trips;
-  // forward window with checkpoints
-  for (int64_t s = 0; s < nseg; ++s) {
-    if ((st = ckpt_save(b, b->ckpts[s])) != LPR_OK) { restore_mode(); return st; }
-    b->since = std::numeric_limits<int64_t>::max() / 2;
-    const int64_t ns = std::min<int64_t>(C, n_steps - s * C);
-    for (int64_t q = 0; q < ns; ++q) enqueue_step(b);
+  // Forward window with checkpoints.  When a particle moves more than skin/2
+  // within a segment the segment was too long for this skin: go back to the
+  // window start and halve the interval (a one-step segment rebuilds its
+  // lists every step and cannot trip).
+  int C = (int)std::min<int64_t>(ckpt_every, n_steps);
+  int64_t nseg = 0;
+  for (;;) {
+    nseg = (n_steps + C - 1) / C;
+    if (!adj_reserve(b, C, (int)nseg + 1)) { restore_mode(); return fail(LPR_E_NOMEM, "adjoint buffers"); }
+    b->R = C;
+    b->R_eff = C;
+    b->skin = C > 1 ? skin : 0.f;
+    if ((st = set_device_skin(b, b->skin)) != LPR_OK) { restore_mode(); return st; }
+    const int64_t trips0 = b->skin_trips;
+    for (int64_t s = 0; s < nseg; ++s) {
+      if ((st = ckpt_save(b, b->ckpts[s])) != LPR_OK) { restore_mode(); return st; }
+      b->since = std::numeric_limits<int64_t>::max() / 2;
+      const int64_t ns = std::min<int64_t>(C, n_steps - s * C);
+      for (int64_t q = 0; q < ns; ++q) enqueue_step(b);
+    }
+    if ((st = sync_check(b)) != LPR_OK) { restore_mode(); return st; }
+    if (b->skin_trips == trips0) break;
+    if ((st = ckpt_restore(b, b->ckpts[0])) != LPR_OK) { restore_mode(); return st; }
+    HIPTRY(hipStreamSynchronize(b->stream));
+    b->base_steps = b->host_steps;
+    b->base_par = cur_par(b);
+    b->plog.clear();
+    C = std::max(1, C / 2);
   }
-  if ((st = sync_check(b)) != LPR_OK) { restore_mode(); return st; }
-  if (b->skin_trips != trips0) {
-    restore_mode();
-    return fail(LPR_E_STATE, "a particle moved more than the skin within a checkpoint segment; "
-                             "use a shorter checkpoint interval");
-  }
+  b->adj_interval = C;
   if ((st = reaction_window_impl(b, 0, body, sum6, &wsteps, 1)) != LPR_OK) { restore_mode(); return st; }
   const double J = sum6[2] / (double)n_steps;
   lpr_bed::Ckpt& end = b->ckpts[nseg];

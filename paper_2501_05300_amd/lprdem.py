@@ -98,7 +98,8 @@ class _Tuning(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("contacts", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("rebuilds", ctypes.c_int64), ("levels", ctypes.c_int32), ("cells", ctypes.c_int64),
-                ("max_owner_slots", ctypes.c_int32), ("skin_trips", ctypes.c_int64)]
+                ("max_owner_slots", ctypes.c_int32), ("skin_trips", ctypes.c_int64),
+                ("adjoint_interval", ctypes.c_int32)]
 
 
 _lib = None

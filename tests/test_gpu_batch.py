@@ -91,3 +91,7 @@ def test_autotuner_returns_a_working_setting():
     tuned.step(30)
     for q in range(len(specs)):
         assert np.array_equal(ref.contacts(bed=q), tuned.contacts(bed=q))
+        # per-particle sums run in stable-id order, whatever the layout
+        xa, va, _ = ref.state(bed=q)
+        xb, vb, _ = tuned.state(bed=q)
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb), q
