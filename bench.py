@@ -65,15 +65,19 @@ def counter_traffic(n_particles):
 def settle_beds(specs, steps, chunk=5000):
     """Relaxes deposited beds in place (positions only), all in one batch,
     with the paper's relaxation friction (mu_t 0.1, mu_r 0.01, frictionless
-    walls), extra normal damping (gamma_n = 50 dt) and dt = 5e-6 s;
-    velocities are then zeroed.  Untimed preparation of the input."""
+    walls), extra normal damping (gamma_n = 10 dt) and dt = 5e-6 s;
+    velocities are then zeroed.  Untimed preparation of the input.
+
+    The damping term is explicit: its rate c/m must stay below 2/dt.  For a
+    1.35 mm sphere under a 24 mm one (overlap ~3e-5 m) gamma_n = 10 dt gives
+    dt c/m ~ 0.6; 50 dt would exceed 2 and eject the fine spheres."""
     import numpy as np
     from paper_2501_05300_amd import beds
     from paper_2501_05300_amd.lprdem import Batch
     work = []
     for spec in specs:
         s = spec.copy()
-        s.params = beds.settle_params(spec.params).replace(dt=5e-6, gamma_factor=50.0)
+        s.params = beds.settle_params(spec.params).replace(dt=5e-6, gamma_factor=10.0)
         for w in s.walls:
             w.mu_t, w.mu_r = 0.0, 0.0
         work.append(s)
@@ -148,6 +152,66 @@ def batch_leg(steps, warmup, settle, tune_steps):
             "graph": "steady cycle replayed as one captured HIP graph"}
 
 
+def adjoint_leg(n, window, ckpt, settle, pre, seed=0):
+    """Adjoint form on the 50k-sphere graded bed (r0 1.5 mm, L 20 mm, k 1,
+    0.2 m deep) under a 0.1 m plate pushed at 0.01 m/s: one reverse-mode
+    window of `window` steps with a checkpoint every `ckpt` steps, timed
+    against the same steps run forward only from the same state."""
+    import torch
+    from paper_2501_05300_amd import beds
+    from paper_2501_05300_amd.lprdem import Bed
+    spec = beds.graded_bed(n, r0=1.5e-3, L=0.02, k=1.0, depth=0.2, seed=seed + 50)
+    log(f"adjoint bed: {spec.n} spheres, side {spec.box[0]:.3f} m")
+    if settle > 0:
+        settle_beds([spec], settle)
+    spec = beds.add_plate(spec, diameter=0.1, speed=0.01)
+    body = spec.info["plate_body"]
+    skin = 0.25 * float(spec.radius.min())
+    bed = Bed(spec, rebuild_every=10, skin=skin)
+    bed.step(pre)
+    bed.sync()
+    x, v, w = bed.state()
+    keys, vals = bed.history()
+    clock = bed.clock()
+
+    def rewind(b):
+        b.set_state(x, v, w)
+        b.set_history(keys, vals)
+        b.set_clock(clock)
+        b.sync()
+
+    def forward(b):
+        rewind(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(window)
+        b.sync()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    plain = Bed(spec)
+    forward(plain)  # warm the captured graph
+    t_plain = forward(plain)
+    plain.close()
+    forward(bed)
+    t_skin = forward(bed)
+    rewind(bed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, g = bed.adjoint_window(window, ckpt, body)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    st = bed.stats()
+    bed.close()
+    log(f"adjoint window {window} steps, checkpoints every {st['adjoint_interval']}: {t_adj:.3f} s; "
+        f"forward {t_plain:.3f} s (every-step lists), {t_skin:.3f} s (skin lists); J {J:.4g} N, grad {g}")
+    return {"spheres": spec.n, "window_steps": window, "checkpoint_every": int(st["adjoint_interval"]),
+            "J_mean_plate_reaction_N": J, "grad_s_k_mu_t_mu_r": [float(q) for q in g],
+            "adjoint_s": t_adj, "forward_every_step_s": t_plain, "forward_skin_s": t_skin,
+            "adjoint_particle_steps_per_s": spec.n * window / t_adj,
+            "adjoint_over_forward_every_step": t_adj / t_plain, "adjoint_over_forward_skin": t_adj / t_skin}
+
+
 def cpu_baseline(spec, pos, vel, omg, keys, vals, clock, steps):
     """The FP64 oracle, as it stands, on the same bed state (bounded sample:
     `steps` steps of the full bed)."""
@@ -182,7 +246,8 @@ def main():
     ap.add_argument("--secondary-skin", type=float, default=0.05,
                     help="skin of the secondary run, as a fraction of the smallest radius")
     ap.add_argument("--batch-steps", type=int, default=300, help="timed steps of the 36-bed leg (0: skip)")
-    ap.add_argument("--batch-settle", type=int, default=10000)
+    ap.add_argument("--batch-settle", type=int, default=40000)
+    ap.add_argument("--adjoint-window", type=int, default=2000, help="steps of the adjoint leg (0: skip)")
     ap.add_argument("--settle", type=int, default=40000,
                     help="relaxation steps before the measurement (paper's reduced friction, damped, dt 5e-6)")
     args = ap.parse_args()
@@ -285,6 +350,8 @@ def main():
     bed.close()
     if args.batch_steps > 0:
         out["batched"] = batch_leg(args.batch_steps, 100, args.batch_settle, 10)
+    if args.adjoint_window > 0:
+        out["adjoint"] = adjoint_leg(50_000, args.adjoint_window, 100, args.settle, 5000, args.seed)
     print(json.dumps(out), flush=True)
 
 

@@ -54,8 +54,7 @@ struct BedConst {
   int32_t body0, nbody;
   int32_t p0, p1;        // padded particle range [p0, p1)
   float skin;
-  float bp_tol;
-  float s_k;             // stiffness multiplier (part of kfac)          // FP32 broad-phase pre-test margin [m]
+  float s_k;             // stiffness multiplier (part of kfac)
   // contact law (FP32) and integration
   float kfac;            // s_k E* / 3  (k_n = kfac sqrt(d*))
   float gn;              // gamma_n = gamma_factor dt

@@ -46,7 +46,8 @@ struct DevBufs {
   int64_t nblk;          // blocks of the smallest step-kernel block size (N / 64)
   // scan scratch
   uint32_t* scan_tmp;
-  float4* posf;          // FP32 (x, y, z, r) written at each rebuild
+  double4* cpos;         // position and radius in cell-list order (rebuild)
+  int32_t* csid;         // stable id in cell-list order (rebuild)
   int32_t* zext;         // [levels][2] occupied z-row range (monotone)
   float* disp;           // distance bound moved since the last rebuild
   uint32_t* viol;        // [2] skin-exceeded flags, by state parity
@@ -104,7 +105,7 @@ struct StepPar {
 void launch_zero(uint32_t* p, int64_t n, hipStream_t st);
 void launch_bin(const DevBufs& d, int s, hipStream_t st);
 void launch_scan(uint32_t* in_out_cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipStream_t st);
-void launch_scatter(const DevBufs& d, hipStream_t st);
+void launch_scatter(const DevBufs& d, int s, hipStream_t st);
 // Owner-side search at state s; reads list/history parity (l_old, h_old) and
 // writes (1-l_old, 1-h_old).
 void launch_search(const DevBufs& d, int s, int l_old, int h_old, hipStream_t st);

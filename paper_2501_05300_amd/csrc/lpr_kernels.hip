@@ -83,9 +83,8 @@ LPR_DEV_INLINE int row_unclamped(const LevelGrid& G, double z) {
   return (int)floor(f);
 }
 
-// Bins every particle into the grid of its own level, writes the compact
-// FP32 copy (x, y, z, r) the search scans, and widens the level's occupied
-// z-row range (monotone, so a stale range is still a superset).
+// Bins every particle into the grid of its own level and widens the level's
+// occupied z-row range (monotone, so a stale range is still a superset).
 __global__ void k_bin(DevBufs d, int s) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= d.N || latched(d.err)) return;
@@ -99,7 +98,6 @@ __global__ void k_bin(DevBufs d, int s) {
   const int32_t c = (int32_t)(G.base + ((int64_t)cz * G.n[1] + cy) * G.n[0] + cx);
   d.pcell[i] = c;
   d.prank[i] = atomicAdd(&d.cell_cnt[c], 1u);
-  d.posf[i] = make_float4((float)p.x, (float)p.y, (float)p.z, (float)p.w);
   const int zu = row_unclamped(G, p.z);
   if (zu < *(const volatile int*)&d.zext[2 * gl]) atomicMin(&d.zext[2 * gl], zu);
   if (zu > *(const volatile int*)&d.zext[2 * gl + 1]) atomicMax(&d.zext[2 * gl + 1], zu);
@@ -109,16 +107,21 @@ void launch_bin(const DevBufs& d, int s, hipStream_t st) {
   hipLaunchKernelGGL(k_bin, dim3((unsigned)((d.N + 255) / 256)), dim3(256), 0, st, d, s);
 }
 
-__global__ void k_scatter(DevBufs d) {
+// Fills the cell lists, with the position, radius and stable id copied
+// alongside so that the search reads each cell's candidates contiguously.
+__global__ void k_scatter(DevBufs d, int s) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= d.N || latched(d.err)) return;
   if (d.meta[i] == INACTIVE) return;
   const int32_t c = d.pcell[i];
-  d.cell_list[d.cell_start[c] + d.prank[i]] = (int32_t)i;
+  const uint32_t q = d.cell_start[c] + d.prank[i];
+  d.cell_list[q] = (int32_t)i;
+  d.cpos[q] = d.pos[s][i];
+  d.csid[q] = d.sid[i];
 }
 
-void launch_scatter(const DevBufs& d, hipStream_t st) {
-  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((d.N + 255) / 256)), dim3(256), 0, st, d);
+void launch_scatter(const DevBufs& d, int s, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((d.N + 255) / 256)), dim3(256), 0, st, d, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -205,14 +208,55 @@ void launch_scan(uint32_t* cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipSt
 
 // ---------------------------------------------------------------------------
 // owner-side search with history carry-over
+//
+// Each thread walks the one-cell neighbourhood of its particle at its own
+// level and every coarser one (a coarser level only when its occupied rows
+// reach the particle's row).  The neighbourhood is at most 3 x 3 rows of up
+// to 3 cells; the cells of a row are consecutive in the cell order, so the
+// row is one range of the cell lists (two where the x axis wraps), and the
+// cell-ordered copies of position, radius and stable id make each range one
+// contiguous read.  All 18 range bounds are loaded before the first
+// candidate, so no candidate read waits on an index read.  The exact FP64
+// predicate runs on every candidate the owner rule keeps; accepted partners
+// collect in LDS, are put in ascending stable id, and inherit their spring
+// history from the previous lists.
 
-constexpr int SEARCH_BS = 128;
+constexpr int SBS = 64;  // threads per search block
 
-__global__ __launch_bounds__(SEARCH_BS) void k_search(DevBufs d, int s, int lo, int ho) {
-  __shared__ int32_t c_sid[K][SEARCH_BS];
-  __shared__ int32_t c_idx[K][SEARCH_BS];
+// Cell ranges [xa, xb) along x covering cx - 1 .. cx + 1 (two pieces where a
+// periodic axis wraps; the whole axis when it has three cells or fewer).
+LPR_DEV_INLINE int x_pieces(const LevelGrid& G, int cx, int xa[2], int xb[2]) {
+  const int n = G.n[0];
+  if (!G.per[0]) {
+    xa[0] = max(0, cx - 1);
+    xb[0] = min(n, cx + 2);
+    return 1;
+  }
+  if (n <= 3) {
+    xa[0] = 0;
+    xb[0] = n;
+    return 1;
+  }
+  if (cx == 0) {
+    xa[0] = 0; xb[0] = 2;
+    xa[1] = n - 1; xb[1] = n;
+    return 2;
+  }
+  if (cx == n - 1) {
+    xa[0] = n - 2; xb[0] = n;
+    xa[1] = 0; xb[1] = 1;
+    return 2;
+  }
+  xa[0] = cx - 1;
+  xb[0] = cx + 2;
+  return 1;
+}
+
+__global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho) {
+  __shared__ int32_t c_sid[K][SBS];
+  __shared__ int32_t c_idx[K][SBS];
   const int t = threadIdx.x;
-  const int64_t i = blockIdx.x * (int64_t)SEARCH_BS + t;
+  const int64_t i = blockIdx.x * (int64_t)SBS + t;
   if (i >= d.N || latched(d.err)) return;
   const int ln = lo ^ 1, hn = ho ^ 1;
   const int64_t N = d.N;
@@ -226,69 +270,76 @@ __global__ __launch_bounds__(SEARCH_BS) void k_search(DevBufs d, int s, int lo, 
     d.cflag[hn][i] = 0u;
     return;
   }
-  const BedConst& bc = d.beds[m >> 8];
+  const BedConst bc = d.beds[m >> 8];
   const int lev_i = (int)(m & 0xffu);
   const double4 pi = d.pos[s][i];
-  const float4 pf = d.posf[i];
-  const float ri = pf.w;
+  const float rif = (float)pi.w;
   const int32_t si = d.sid[i];
   const double skin = (double)bc.skin;
-  const float Lx = (float)bc.L[0], Ly = (float)bc.L[1];
-  const bool perx = (bc.periodic & 1u) != 0, pery = (bc.periodic & 2u) != 0;
-  const float reach = ri + bc.skin + bc.bp_tol;
   int cnt = 0;
-  bool ovf = false;
   for (int lev = lev_i; lev < bc.nlev; ++lev) {
-    const LevelGrid& G = d.levels[bc.lev0 + lev];
+    const int gl = bc.lev0 + lev;
+    const LevelGrid G = d.levels[gl];
     if (lev > lev_i) {
       // a coarser level whose particles all sit more than one row away
       // cannot touch this particle
       const int zu = row_unclamped(G, pi.z);
-      const int gl = bc.lev0 + lev;
       if (zu < d.zext[2 * gl] - 1 || zu > d.zext[2 * gl + 1] + 1) continue;
     }
-    int lx[3], ly[3], lz[3];
-    const int nxl = axis_neighbours(G, 0, cell_axis(G, 0, pi.x), lx);
+    int ly[3], lz[3], xa[2], xb[2];
     const int nyl = axis_neighbours(G, 1, cell_axis(G, 1, pi.y), ly);
     const int nzl = axis_neighbours(G, 2, cell_axis(G, 2, pi.z), lz);
-    for (int a = 0; a < nzl; ++a)
-      for (int b = 0; b < nyl; ++b)
-        for (int e = 0; e < nxl; ++e) {
-          const int64_t c = G.base + ((int64_t)lz[a] * G.n[1] + ly[b]) * G.n[0] + lx[e];
-          const uint32_t c0 = d.cell_start[c], c1 = d.cell_start[c + 1];
-          for (uint32_t q = c0; q < c1; ++q) {
-            const int32_t j = d.cell_list[q];
-            // conservative FP32 pre-test on the compact copy; the FP64
-            // predicate below decides
-            const float4 qf = d.posf[j];
-            if (qf.w < ri) continue;  // j owns the pair
-            float fx = qf.x - pf.x, fy = qf.y - pf.y;
-            const float fz = qf.z - pf.z;
-            if (perx) fx = (fx > 0.5f * Lx) ? fx - Lx : ((fx < -0.5f * Lx) ? fx + Lx : fx);
-            if (pery) fy = (fy > 0.5f * Ly) ? fy - Ly : ((fy < -0.5f * Ly) ? fy + Ly : fy);
-            const float Rf = reach + qf.w;
-            if (fx * fx + fy * fy + fz * fz >= Rf * Rf) continue;
-            const int32_t sj = d.sid[j];
-            if (qf.w == ri && sj <= si) continue;  // equal radii: smaller id owns
-            const double4 pj = d.pos[s][j];
-            double dx, dy, dz;
-            const double d2 = pair_sep(bc, pi, pj, dx, dy, dz);
-            if (within_skin(d2, pi.w, pj.w, skin)) {
-              if (cnt < K) {
-                c_sid[cnt][t] = sj;
-                c_idx[cnt][t] = j;
-              } else {
-                ovf = true;
-              }
-              ++cnt;
+    const int nxp = x_pieces(G, cell_axis(G, 0, pi.x), xa, xb);
+    // every range bound first
+    uint32_t q0[18], q1[18];
+#pragma unroll
+    for (int r = 0; r < 18; ++r) {
+      const int a = r / 6, b = (r / 2) % 3, p = r & 1;
+      q0[r] = 0u;
+      q1[r] = 0u;
+      if (a < nzl && b < nyl && p < nxp) {
+        const int64_t rb = G.base + ((int64_t)lz[a] * G.n[1] + ly[b]) * G.n[0];
+        q0[r] = d.cell_start[rb + xa[p]];
+        q1[r] = d.cell_start[rb + xb[p]];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 18; ++r) {
+      // four candidates per round, their reads issued together
+      for (uint32_t q = q0[r]; q < q1[r]; q += 4) {
+        double4 pj[4];
+        int32_t sj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t qq = (q + u < q1[r]) ? q + u : q;
+          pj[u] = d.cpos[qq];
+          sj[u] = d.csid[qq];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (q + u >= q1[r]) break;
+          const float rjf = (float)pj[u].w;
+          if (rjf < rif) continue;  // j owns the pair
+          if (rjf == rif && sj[u] <= si) continue;  // equal radii: smaller id owns (and not itself)
+          double dx, dy, dz;
+          const double d2 = pair_sep(bc, pi, pj[u], dx, dy, dz);
+          if (within_skin(d2, pi.w, pj[u].w, skin)) {
+            if (cnt < K) {
+              c_sid[cnt][t] = sj[u];
+              c_idx[cnt][t] = (int32_t)(q + u);
             }
+            ++cnt;
           }
         }
+      }
+    }
   }
-  if (ovf) {
+  if (cnt > K) {
     atomicOr(d.err, ERR_CAPACITY);
     cnt = K;
   }
+  // cell-list positions -> storage indices
+  for (int a = 0; a < cnt; ++a) c_idx[a][t] = d.cell_list[c_idx[a][t]];
   // canonical slot order: ascending partner stable id
   for (int a = 1; a < cnt; ++a) {
     const int32_t ks = c_sid[a][t], kj = c_idx[a][t];
@@ -332,8 +383,7 @@ __global__ __launch_bounds__(SEARCH_BS) void k_search(DevBufs d, int s, int lo, 
 }
 
 void launch_search(const DevBufs& d, int s, int lo, int ho, hipStream_t st) {
-  hipLaunchKernelGGL(k_search, dim3((unsigned)((d.N + SEARCH_BS - 1) / SEARCH_BS)), dim3(SEARCH_BS), 0, st, d, s,
-                     lo, ho);
+  hipLaunchKernelGGL(k_search, dim3((unsigned)((d.N + SBS - 1) / SBS)), dim3(SBS), 0, st, d, s, lo, ho);
 }
 
 __global__ void k_rev_scatter(DevBufs d, int l) {

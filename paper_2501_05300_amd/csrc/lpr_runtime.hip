@@ -379,7 +379,7 @@ void enqueue_rebuild(lpr_bed* b) {
   launch_zero(d.rev_cnt, d.N, b->stream);
   launch_bin(d, b->s, b->stream);
   launch_scan(d.cell_cnt, d.cell_start, d.scan_tmp, d.ncells, b->stream);
-  launch_scatter(d, b->stream);
+  launch_scatter(d, b->s, b->stream);
   launch_search(d, b->s, b->l, b->h, b->stream);
   b->l ^= 1;
   b->h ^= 1;
@@ -537,7 +537,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   ok &= dal(b, &d.sid, N) && dal(b, &d.meta, N) && dal(b, &d.chunk_bed32, N / PAD);
   ok &= dal(b, &d.cell_cnt, cell_base) && dal(b, &d.cell_start, cell_base + 1);
   ok &= dal(b, &d.pcell, N) && dal(b, &d.prank, N) && dal(b, &d.cell_list, N);
-  ok &= dal(b, &d.posf, N) && dal(b, &d.zext, 2 * levels.size());
+  ok &= dal(b, &d.cpos, N) && dal(b, &d.csid, N) && dal(b, &d.zext, 2 * levels.size());
   ok &= dal(b, &d.disp, N) && dal(b, &d.viol, 2);
   ok &= dal(b, &d.own_rank, (size_t)K * N) && dal(b, &d.rev_cnt, N) && dal(b, &d.rev_start, N + 1);
   ok &= dal(b, &d.rev_ent, (size_t)K * N);
@@ -598,12 +598,6 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
     C.p0 = (int32_t)H.p0;
     C.p1 = (int32_t)(H.p0 + H.npad);
     C.skin = b->skin;
-    {
-      // margin of the FP32 pre-test: 32 ulp of the largest coordinate
-      double mc = std::max(std::fabs(D->box[0]), std::fabs(D->box[1]));
-      for (int64_t i = 0; i < 3 * D->n; ++i) mc = std::max(mc, std::fabs(D->pos[i]));
-      C.bp_tol = (float)(32.0 * std::ldexp(1.0, std::ilogb(std::max(mc, 1e-3)) - 23));
-    }
     const double Estar = 1.0 / ((1.0 - P.nu * P.nu) / P.E + (1.0 - P.nu * P.nu) / P.E);
     C.kfac = (float)(P.s_k * Estar / 3.0);
     C.s_k = (float)P.s_k;
