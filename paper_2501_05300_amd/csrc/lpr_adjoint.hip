@@ -32,8 +32,8 @@ __global__ void k_adj_pre(DevBufs d, AdjBufs a, int q) {
   if (m == INACTIVE) return;
   const BedConst& bc = d.beds[m >> 8];
   const int64_t N = d.N;
-  const float4 v = a.vel[(int64_t)q * N + i];
-  const float4 w = a.omg[(int64_t)q * N + i];
+  const float4 v = a.st[(int64_t)q * N + i].v;
+  const float4 w = a.st[(int64_t)q * N + i].w;
   const float4 xb = a.xb[i], vb = a.vb[i], wb = a.wb[i];
   // x' = x + dt v'  ->  adjoint of v' gains dt xb
   const float vx = vb.x + bc.dt * xb.x, vy = vb.y + bc.dt * xb.y, vz = vb.z + bc.dt * xb.z;
@@ -135,14 +135,12 @@ __global__ __launch_bounds__(ADJ_BS) void k_adj_step(DevBufs d, AdjBufs a, int q
   if (m == INACTIVE) return;
   const BedConst bc = d.beds[m >> 8];
   const int hn = hp ^ 1;
-  const double4* P = a.pos + (int64_t)q * N;
-  const float4* V = a.vel + (int64_t)q * N;
-  const float4* Wv = a.omg + (int64_t)q * N;
+  const PState* S = a.st + (int64_t)q * N;
   const uint32_t* CF = a.cflag + (int64_t)q * N;
-  const float4* HA = a.hA + (int64_t)q * K * N;
-  const float2* HB = a.hB + (int64_t)q * K * N;
-  const double4 xi = P[i];
-  const float4 vi = V[i], wi = Wv[i];
+  const HRec* HS = a.hist + (int64_t)q * K * N;
+  const PState me = S[i];
+  const double4 xi = me.x;
+  const float4 vi = me.v, wi = me.w;
   const float3 Fbi = ld3(a.Fb[i]), Tbi = ld3(a.Tb[i]);
   float3 xba = zero3(), vba = zero3(), wba = zero3();
   double th0 = 0.0, th1 = 0.0, th2 = 0.0;
@@ -165,8 +163,9 @@ __global__ __launch_bounds__(ADJ_BS) void k_adj_step(DevBufs d, AdjBufs a, int q
       qq = i;
     }
     const int64_t other = mine ? qq : o;
-    const double4 xo_ = P[other];
-    const float4 vo_ = V[other], wo_ = Wv[other];
+    const PState ot = S[other];
+    const double4 xo_ = ot.x;
+    const float4 vo_ = ot.v, wo_ = ot.w;
     const double4 xa = mine ? xi : xo_, xb = mine ? xo_ : xi;
     const float4 va = mine ? vi : vo_, vb = mine ? vo_ : vi;
     const float4 wa = mine ? wi : wo_, wb = mine ? wo_ : wi;
@@ -183,10 +182,9 @@ __global__ __launch_bounds__(ADJ_BS) void k_adj_step(DevBufs d, AdjBufs a, int q
     const bool valid = (fo >> k) & 1u;
     LawIn in;
     if (valid) {
-      const float4 a4 = HA[k * N + o];
-      const float2 b2 = HB[k * N + o];
-      in.xt = f3(a4.x, a4.y, a4.z);
-      in.xr = f3(a4.w, b2.x, b2.y);
+      const HRec hr = HS[k * N + o];
+      in.xt = f3(hr.t.x, hr.t.y, hr.t.z);
+      in.xr = f3(hr.r.x, hr.r.y, hr.r.z);
     } else {
       in.xt = zero3();
       in.xr = zero3();

@@ -2,14 +2,14 @@
 //
 // Layout in HBM (all arrays in storage order = beds back to back, each bed
 // padded to a multiple of PAD particles, Morton order per radius band):
-//   pos[2][N]  double4  x, y, z, r             (ping-pong by step parity)
-//   vel[2][N]  float4   v, 1/m
-//   omg[2][N]  float4   omega, 1/I
+//   st[2][N]   PState (64 B)  position and radius (double4), velocity and
+//              1/m (float4), angular velocity and 1/I (float4), one aligned
+//              record per particle (ping-pong by step parity)
 //   sid[N]     int32    stable id inside the bed
 //   meta[N]    uint32   bed << 8 | level, INACTIVE for padding
 //   own_idx[2][K][N] int32   owner-side candidate partners (slot-major)
 //   own_cnt[2][N]    int32
-//   hA[2][K][N] float4 (xi_t, xi_r.x), hB[2][K][N] float2 (xi_r.y, xi_r.z)
+//   hist[2][K][N] HRec (xi_t, xi_r); zero for a slot out of contact
 //   wA[2][W][N], wB[2][W][N]  the same for walls, indexed by wall
 //   cflag[2][N] uint32 bit k: owner slot k in contact; bit 16+w: wall w
 //   rev_start[N+1], rev_ent[*]  reverse (partner-side) entries, packed
@@ -20,6 +20,22 @@
 #include <stdint.h>
 
 namespace lpr {
+
+// State of one particle: one 64-byte record, so a partner's state is a
+// single aligned read.
+struct PState {
+  double4 x;  // x, y, z, r
+  float4 v;   // velocity, 1/m
+  float4 w;   // angular velocity, 1/I
+};
+
+// Spring history of one contact slot, 32 bytes so that the partner side of
+// a contact reads it as one sector.
+struct HRec {
+  float4 t;  // tangential spring xi_t (w unused)
+  float4 r;  // rolling spring xi_r (w unused)
+};
+
 
 constexpr int K = 16;            // sphere contacts per owner
 constexpr int MAXW = 16;         // walls per bed

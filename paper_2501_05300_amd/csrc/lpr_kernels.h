@@ -13,9 +13,7 @@ struct DevBufs {
   int32_t nbeds;
   int64_t ncells;
   // state
-  double4* pos[2];
-  float4* vel[2];
-  float4* omg[2];
+  PState* st[2];
   int32_t* sid;
   uint32_t* meta;
   uint8_t* chunk_bed;   // bed of each PAD-chunk of particles (as int32 below)
@@ -34,8 +32,7 @@ struct DevBufs {
   uint32_t* rev_start;   // [N+1]
   uint32_t* rev_ent;     // [K*N]
   // history
-  float4* hA[2];         // [K][N]
-  float2* hB[2];
+  HRec* hist[2];         // [K][N]
   float4* wA[2];         // [MAXW][N]
   float2* wB[2];
   uint32_t* cflag[2];
@@ -68,12 +65,9 @@ struct DevBufs {
 // candidate lists, the running adjoints and per-particle FP64 parameter
 // adjoints.
 struct AdjBufs {
-  double4* pos;          // [steps][N]
-  float4* vel;           // [steps][N]
-  float4* omg;           // [steps][N]
+  PState* st;            // [steps][N]
   uint32_t* cflag;       // [steps][N]
-  float4* hA;            // [steps][K][N]
-  float2* hB;
+  HRec* hist;            // [steps][K][N]
   float4* wA;            // [steps][nwall_max][N]
   float2* wB;
   WallPose* walls;       // [steps][nwall_total]

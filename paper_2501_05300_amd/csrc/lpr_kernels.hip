@@ -73,6 +73,16 @@ LPR_DEV_INLINE int axis_neighbours(const LevelGrid& G, int a, int c, int out[3])
   return m;
 }
 
+// Work block handled by launch block b of a grid of g blocks: the blocks
+// that the hardware places on one XCD (b mod 8) take one contiguous range of
+// particles, so neighbours they gather share that XCD's L2.
+LPR_DEV_INLINE int64_t xcd_block(int64_t b, int64_t g) {
+  const int64_t chunk = (g + 7) / 8;
+  const int64_t x = b & 7, q = b >> 3;
+  const int64_t w = x * chunk + q;
+  return w < g ? w : -1;
+}
+
 // ---------------------------------------------------------------------------
 // binning
 
@@ -93,7 +103,7 @@ __global__ void k_bin(DevBufs d, int s) {
   const BedConst& bc = d.beds[m >> 8];
   const int gl = bc.lev0 + (int)(m & 0xffu);
   const LevelGrid& G = d.levels[gl];
-  const double4 p = d.pos[s][i];
+  const double4 p = d.st[s][i].x;
   const int cx = cell_axis(G, 0, p.x), cy = cell_axis(G, 1, p.y), cz = cell_axis(G, 2, p.z);
   const int32_t c = (int32_t)(G.base + ((int64_t)cz * G.n[1] + cy) * G.n[0] + cx);
   d.pcell[i] = c;
@@ -116,7 +126,7 @@ __global__ void k_scatter(DevBufs d, int s) {
   const int32_t c = d.pcell[i];
   const uint32_t q = d.cell_start[c] + d.prank[i];
   d.cell_list[q] = (int32_t)i;
-  d.cpos[q] = d.pos[s][i];
+  d.cpos[q] = d.st[s][i].x;
   d.csid[q] = d.sid[i];
 }
 
@@ -256,7 +266,11 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
   __shared__ int32_t c_sid[K][SBS];
   __shared__ int32_t c_idx[K][SBS];
   const int t = threadIdx.x;
-  const int64_t i = blockIdx.x * (int64_t)SBS + t;
+  // each XCD takes one contiguous range of particles, so the neighbour rows
+  // its blocks read overlap in that XCD's L2
+  const int64_t blk = xcd_block(blockIdx.x, (d.N + SBS - 1) / SBS);
+  if (blk < 0) return;
+  const int64_t i = blk * SBS + t;
   if (i >= d.N || latched(d.err)) return;
   const int ln = lo ^ 1, hn = ho ^ 1;
   const int64_t N = d.N;
@@ -272,7 +286,7 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
   }
   const BedConst bc = d.beds[m >> 8];
   const int lev_i = (int)(m & 0xffu);
-  const double4 pi = d.pos[s][i];
+  const double4 pi = d.st[s][i].x;
   const float rif = (float)pi.w;
   const int32_t si = d.sid[i];
   const double skin = (double)bc.skin;
@@ -359,16 +373,21 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
     const int32_t j = c_idx[k][t];
     d.own_idx[ln][k * N + i] = j;
     d.own_rank[k * N + i] = atomicAdd(&d.rev_cnt[j], 1u);
+    // a slot whose pair was not in contact holds zero history, so readers
+    // need not consult the contact flags
+    HRec hr;
+    hr.t = make_float4(0.f, 0.f, 0.f, 0.f);
+    hr.r = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int k2 = 0; k2 < cnt_old; ++k2) {
       if (d.own_idx[lo][k2 * N + i] == j) {
         if ((fo >> k2) & 1u) {
-          d.hA[hn][k * N + i] = d.hA[ho][k2 * N + i];
-          d.hB[hn][k * N + i] = d.hB[ho][k2 * N + i];
+          hr = d.hist[ho][k2 * N + i];
           fn |= 1u << k;
         }
         break;
       }
     }
+    d.hist[hn][k * N + i] = hr;
   }
   for (int w = 0; w < bc.nwall; ++w)
     if ((fo >> (WALL_BIT + w)) & 1u) {
@@ -383,7 +402,8 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
 }
 
 void launch_search(const DevBufs& d, int s, int lo, int ho, hipStream_t st) {
-  hipLaunchKernelGGL(k_search, dim3((unsigned)((d.N + SBS - 1) / SBS)), dim3(SBS), 0, st, d, s, lo, ho);
+  const int64_t g = (d.N + SBS - 1) / SBS;
+  hipLaunchKernelGGL(k_search, dim3((unsigned)((g + 7) / 8 * 8)), dim3(SBS), 0, st, d, s, lo, ho);
 }
 
 __global__ void k_rev_scatter(DevBufs d, int l) {
@@ -434,16 +454,6 @@ LPR_DEV_INLINE double wave_sum(double v) {
   return v;
 }
 
-// Work block handled by launch block b of a grid of g blocks: the blocks
-// that the hardware places on one XCD (b mod 8) take one contiguous range of
-// particles, so neighbours they gather share that XCD's L2.
-LPR_DEV_INLINE int64_t xcd_block(int64_t b, int64_t g) {
-  const int64_t chunk = (g + 7) / 8;
-  const int64_t x = b & 7, q = b >> 3;
-  const int64_t w = x * chunk + q;
-  return w < g ? w : -1;
-}
-
 // One work block of the fused step (all threads of the launch block).
 template <int BS>
 __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, int record, int64_t blk) {
@@ -473,10 +483,10 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
   float3 F = f3(0.f, 0.f, 0.f), T = f3(0.f, 0.f, 0.f);
   uint32_t fnew = 0u;
   if (active) {
-    xi = d.pos[s][i];
-    vi = d.vel[s][i];
-    wi = d.omg[s][i];
-    const uint32_t fold = d.cflag[h][i];
+    const PState me = d.st[s][i];
+    xi = me.x;
+    vi = me.v;
+    wi = me.w;
     const int n_own = d.own_cnt[l][i];
     const uint32_t rs = d.rev_start[i];
     const int n_tot = n_own + (int)(d.rev_start[i + 1] - rs);
@@ -495,25 +505,30 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
         q = i;
       }
       const int64_t other = mine ? q : o;
-      const double4 xo_ = d.pos[s][other];
-      const float4 vo_ = d.vel[s][other];
-      const float4 wo_ = d.omg[s][other];
+      const PState ot = d.st[s][other];
+      const double4 xo_ = ot.x;
+      const float4 vo_ = ot.v;
+      const float4 wo_ = ot.w;
       const double4 xa = mine ? xi : xo_, xb = mine ? xo_ : xi;   // owner a, partner b
       const float4 va = mine ? vi : vo_, vb = mine ? vo_ : vi;
       const float4 wa = mine ? wi : wo_, wb = mine ? wo_ : wi;
       double dx, dy, dz;
       const double d2 = pair_sep(bc, xa, xb, dx, dy, dz);
-      if (!sphere_touch(d2, xa.w, xb.w)) continue;
-      const uint32_t fo = mine ? fold : d.cflag[h][o];
+      if (!sphere_touch(d2, xa.w, xb.w)) {
+        if (mine) {  // out of contact: the slot keeps no history
+          HRec z;
+          z.t = make_float4(0.f, 0.f, 0.f, 0.f);
+          z.r = make_float4(0.f, 0.f, 0.f, 0.f);
+          d.hist[hn][k * N + i] = z;
+        }
+        continue;
+      }
+      // slots out of contact hold zeros, so the history is read as it is
       LawIn in;
-      if ((fo >> k) & 1u) {
-        const float4 a4 = d.hA[h][k * N + o];
-        const float2 b2 = d.hB[h][k * N + o];
-        in.xt = f3(a4.x, a4.y, a4.z);
-        in.xr = f3(a4.w, b2.x, b2.y);
-      } else {
-        in.xt = f3(0.f, 0.f, 0.f);
-        in.xr = f3(0.f, 0.f, 0.f);
+      {
+        const HRec hr = d.hist[h][k * N + o];
+        in.xt = f3(hr.t.x, hr.t.y, hr.t.z);
+        in.xr = f3(hr.r.x, hr.r.y, hr.r.z);
       }
       // overlap in FP64 (it is a small difference of large numbers); the
       // unit normal only needs FP32
@@ -540,8 +555,10 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
       if (mine) {
         F = F + out.F;
         T = T + (la * nft + out.M);
-        d.hA[hn][k * N + i] = make_float4(out.xt.x, out.xt.y, out.xt.z, out.xr.x);
-        d.hB[hn][k * N + i] = make_float2(out.xr.y, out.xr.z);
+        HRec hr;
+        hr.t = make_float4(out.xt.x, out.xt.y, out.xt.z, 0.f);
+        hr.r = make_float4(out.xr.x, out.xr.y, out.xr.z, 0.f);
+        d.hist[hn][k * N + i] = hr;
         fnew |= 1u << k;
       } else {
         F = F - out.F;
@@ -653,9 +670,11 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
     d.disp[i] = moved;
     if (moved > 0.45f * bc.skin) atomicOr(&d.viol[sn], 1u);
   }
-  d.pos[sn][i] = make_double4(x, y, z, xi.w);
-  d.vel[sn][i] = make_float4(vx, vy, vz, vi.w);
-  d.omg[sn][i] = make_float4(ox, oy, oz, wi.w);
+  PState out;
+  out.x = make_double4(x, y, z, xi.w);
+  out.v = make_float4(vx, vy, vz, vi.w);
+  out.w = make_float4(ox, oy, oz, wi.w);
+  d.st[sn][i] = out;
 }
 
 // One launch block per work block, XCD-aware placement.

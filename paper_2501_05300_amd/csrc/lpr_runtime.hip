@@ -134,8 +134,8 @@ struct lpr_bed {
   int adj_ckpts = 0;      // checkpoints available
   int adj_interval = 0;   // checkpoint interval the last adjoint window used
   struct Ckpt {
-    double4* pos; float4* vel; float4* omg;
-    uint32_t* cflag; float4* hA; float2* hB; float4* wA; float2* wB;
+    PState* st;
+    uint32_t* cflag; HRec* hist; float4* wA; float2* wB;
     int32_t* own_cnt; int32_t* own_idx;
     BedDyn* bedyn; BodyDyn* bdyn;
     int s, h, l;
@@ -528,9 +528,9 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   d.ncells = cell_base;
   bool ok = true;
   for (int q = 0; q < 2; ++q) {
-    ok &= dal(b, &d.pos[q], N) && dal(b, &d.vel[q], N) && dal(b, &d.omg[q], N);
+    ok &= dal(b, &d.st[q], N);
     ok &= dal(b, &d.own_idx[q], (size_t)K * N) && dal(b, &d.own_cnt[q], N);
-    ok &= dal(b, &d.hA[q], (size_t)K * N) && dal(b, &d.hB[q], (size_t)K * N);
+    ok &= dal(b, &d.hist[q], (size_t)K * N);
     ok &= dal(b, &d.wA[q], (size_t)max_walls * N) && dal(b, &d.wB[q], (size_t)max_walls * N);
     ok &= dal(b, &d.cflag[q], N);
   }
@@ -557,8 +557,12 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   }
 
   // host images
-  std::vector<double4> hpos(N, make_double4(0, 0, 0, 0));
-  std::vector<float4> hvel(N, make_float4(0, 0, 0, 0)), homg(N, make_float4(0, 0, 0, 0));
+  std::vector<PState> hst(N);
+  for (PState& p : hst) {
+    p.x = make_double4(0, 0, 0, 0);
+    p.v = make_float4(0, 0, 0, 0);
+    p.w = make_float4(0, 0, 0, 0);
+  }
   std::vector<int32_t> hsid(N, -1), hchunk(N / PAD, 0);
   std::vector<uint32_t> hmeta(N, INACTIVE);
   std::vector<BedConst> hbc(nb);
@@ -576,11 +580,11 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
       const double r = (double)D->radius[i];
       const double m = P.rho * (4.0 / 3.0) * M_PI * r * r * r;
       const double I = 0.4 * m * r * r;
-      hpos[sidx] = make_double4(D->pos[3 * i], D->pos[3 * i + 1], D->pos[3 * i + 2], r);
-      hvel[sidx] = make_float4(D->vel ? D->vel[3 * i] : 0.f, D->vel ? D->vel[3 * i + 1] : 0.f,
-                               D->vel ? D->vel[3 * i + 2] : 0.f, (float)(1.0 / m));
-      homg[sidx] = make_float4(D->omega ? D->omega[3 * i] : 0.f, D->omega ? D->omega[3 * i + 1] : 0.f,
-                               D->omega ? D->omega[3 * i + 2] : 0.f, (float)(1.0 / I));
+      hst[sidx].x = make_double4(D->pos[3 * i], D->pos[3 * i + 1], D->pos[3 * i + 2], r);
+      hst[sidx].v = make_float4(D->vel ? D->vel[3 * i] : 0.f, D->vel ? D->vel[3 * i + 1] : 0.f,
+                                D->vel ? D->vel[3 * i + 2] : 0.f, (float)(1.0 / m));
+      hst[sidx].w = make_float4(D->omega ? D->omega[3 * i] : 0.f, D->omega ? D->omega[3 * i + 1] : 0.f,
+                                D->omega ? D->omega[3 * i + 2] : 0.f, (float)(1.0 / I));
       hsid[sidx] = (int32_t)i;
       hmeta[sidx] = ((uint32_t)q << 8) | lev_of[q][i];
     }
@@ -650,12 +654,8 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
   };
   hipError_t e = hipSuccess;
-  e = (hipError_t)(e | up(d.pos[0], hpos.data(), sizeof(double4) * N));
-  e = (hipError_t)(e | up(d.pos[1], hpos.data(), sizeof(double4) * N));
-  e = (hipError_t)(e | up(d.vel[0], hvel.data(), sizeof(float4) * N));
-  e = (hipError_t)(e | up(d.vel[1], hvel.data(), sizeof(float4) * N));
-  e = (hipError_t)(e | up(d.omg[0], homg.data(), sizeof(float4) * N));
-  e = (hipError_t)(e | up(d.omg[1], homg.data(), sizeof(float4) * N));
+  e = (hipError_t)(e | up(d.st[0], hst.data(), sizeof(PState) * N));
+  e = (hipError_t)(e | up(d.st[1], hst.data(), sizeof(PState) * N));
   e = (hipError_t)(e | up(d.sid, hsid.data(), sizeof(int32_t) * N));
   e = (hipError_t)(e | up(d.meta, hmeta.data(), sizeof(uint32_t) * N));
   e = (hipError_t)(e | up(d.chunk_bed32, hchunk.data(), sizeof(int32_t) * (N / PAD)));
@@ -668,6 +668,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   for (int q = 0; q < 2; ++q) {
     e = (hipError_t)(e | hipMemsetAsync(d.own_cnt[q], 0, sizeof(int32_t) * N, st));
     e = (hipError_t)(e | hipMemsetAsync(d.cflag[q], 0, sizeof(uint32_t) * N, st));
+    e = (hipError_t)(e | hipMemsetAsync(d.hist[q], 0, sizeof(HRec) * K * N, st));
   }
   e = (hipError_t)(e | hipMemsetAsync(d.err, 0, sizeof(uint32_t), st));
   e = (hipError_t)(e | hipMemsetAsync(d.stat, 0, sizeof(uint32_t) * 4, st));
@@ -813,16 +814,14 @@ static lpr_status get_state_impl(lpr_bed* b, int32_t bed, double* pos, float* ve
   lpr_status st = state_parity(b, &par);
   if (st != LPR_OK) return st;
   const HostBed& H = b->hb[bed];
-  std::vector<double4> hp(H.npad);
-  std::vector<float4> hv(H.npad), hw(H.npad);
-  HIPTRY(hipMemcpy(hp.data(), b->d.pos[par] + H.p0, sizeof(double4) * H.npad, hipMemcpyDeviceToHost));
-  HIPTRY(hipMemcpy(hv.data(), b->d.vel[par] + H.p0, sizeof(float4) * H.npad, hipMemcpyDeviceToHost));
-  HIPTRY(hipMemcpy(hw.data(), b->d.omg[par] + H.p0, sizeof(float4) * H.npad, hipMemcpyDeviceToHost));
+  std::vector<PState> hs(H.npad);
+  HIPTRY(hipMemcpy(hs.data(), b->d.st[par] + H.p0, sizeof(PState) * H.npad, hipMemcpyDeviceToHost));
   for (int64_t off = 0; off < H.n; ++off) {
     const int64_t q = H.perm[off];
-    if (pos) { pos[3 * q] = hp[off].x; pos[3 * q + 1] = hp[off].y; pos[3 * q + 2] = hp[off].z; }
-    if (vel) { vel[3 * q] = hv[off].x; vel[3 * q + 1] = hv[off].y; vel[3 * q + 2] = hv[off].z; }
-    if (omega) { omega[3 * q] = hw[off].x; omega[3 * q + 1] = hw[off].y; omega[3 * q + 2] = hw[off].z; }
+    const PState& p = hs[off];
+    if (pos) { pos[3 * q] = p.x.x; pos[3 * q + 1] = p.x.y; pos[3 * q + 2] = p.x.z; }
+    if (vel) { vel[3 * q] = p.v.x; vel[3 * q + 1] = p.v.y; vel[3 * q + 2] = p.v.z; }
+    if (omega) { omega[3 * q] = p.w.x; omega[3 * q + 1] = p.w.y; omega[3 * q + 2] = p.w.z; }
   }
   return LPR_OK;
 }
@@ -837,20 +836,16 @@ static lpr_status set_state_impl(lpr_bed* b, int32_t bed, const double* pos, con
   int par = 0;
   lpr_status st = state_parity(b, &par);
   if (st != LPR_OK) return st;
-  std::vector<double4> hp(H.npad);
-  std::vector<float4> hv(H.npad), hw(H.npad);
-  HIPTRY(hipMemcpy(hp.data(), b->d.pos[par] + H.p0, sizeof(double4) * H.npad, hipMemcpyDeviceToHost));
-  HIPTRY(hipMemcpy(hv.data(), b->d.vel[par] + H.p0, sizeof(float4) * H.npad, hipMemcpyDeviceToHost));
-  HIPTRY(hipMemcpy(hw.data(), b->d.omg[par] + H.p0, sizeof(float4) * H.npad, hipMemcpyDeviceToHost));
+  std::vector<PState> hs(H.npad);
+  HIPTRY(hipMemcpy(hs.data(), b->d.st[par] + H.p0, sizeof(PState) * H.npad, hipMemcpyDeviceToHost));
   for (int64_t off = 0; off < H.n; ++off) {
     const int64_t q = H.perm[off];
-    if (pos) { hp[off].x = pos[3 * q]; hp[off].y = pos[3 * q + 1]; hp[off].z = pos[3 * q + 2]; }
-    if (vel) { hv[off].x = vel[3 * q]; hv[off].y = vel[3 * q + 1]; hv[off].z = vel[3 * q + 2]; }
-    if (omega) { hw[off].x = omega[3 * q]; hw[off].y = omega[3 * q + 1]; hw[off].z = omega[3 * q + 2]; }
+    PState& p = hs[off];
+    if (pos) { p.x.x = pos[3 * q]; p.x.y = pos[3 * q + 1]; p.x.z = pos[3 * q + 2]; }
+    if (vel) { p.v.x = vel[3 * q]; p.v.y = vel[3 * q + 1]; p.v.z = vel[3 * q + 2]; }
+    if (omega) { p.w.x = omega[3 * q]; p.w.y = omega[3 * q + 1]; p.w.z = omega[3 * q + 2]; }
   }
-  HIPTRY(hipMemcpy(b->d.pos[par] + H.p0, hp.data(), sizeof(double4) * H.npad, hipMemcpyHostToDevice));
-  HIPTRY(hipMemcpy(b->d.vel[par] + H.p0, hv.data(), sizeof(float4) * H.npad, hipMemcpyHostToDevice));
-  HIPTRY(hipMemcpy(b->d.omg[par] + H.p0, hw.data(), sizeof(float4) * H.npad, hipMemcpyHostToDevice));
+  HIPTRY(hipMemcpy(b->d.st[par] + H.p0, hs.data(), sizeof(PState) * H.npad, hipMemcpyHostToDevice));
   b->since = std::numeric_limits<int64_t>::max() / 2;  // positions moved: rebuild before the next step
   return LPR_OK;
 }
@@ -863,14 +858,14 @@ static lpr_status get_history_impl(lpr_bed* b, int32_t bed, lpr_history* out, in
   const int64_t N = b->d.N;
   std::vector<int32_t> cnt(N), idx((size_t)K * N), sid(N);
   std::vector<uint32_t> fl(N);
-  std::vector<float4> a((size_t)K * N), wa((size_t)b->max_walls * N);
-  std::vector<float2> c((size_t)K * N), wc((size_t)b->max_walls * N);
+  std::vector<HRec> a((size_t)K * N);
+  std::vector<float4> wa((size_t)b->max_walls * N);
+  std::vector<float2> wc((size_t)b->max_walls * N);
   HIPTRY(hipMemcpy(cnt.data(), b->d.own_cnt[b->l], sizeof(int32_t) * N, hipMemcpyDeviceToHost));
   HIPTRY(hipMemcpy(idx.data(), b->d.own_idx[b->l], sizeof(int32_t) * K * N, hipMemcpyDeviceToHost));
   HIPTRY(hipMemcpy(sid.data(), b->d.sid, sizeof(int32_t) * N, hipMemcpyDeviceToHost));
   HIPTRY(hipMemcpy(fl.data(), b->d.cflag[b->h], sizeof(uint32_t) * N, hipMemcpyDeviceToHost));
-  HIPTRY(hipMemcpy(a.data(), b->d.hA[b->h], sizeof(float4) * K * N, hipMemcpyDeviceToHost));
-  HIPTRY(hipMemcpy(c.data(), b->d.hB[b->h], sizeof(float2) * K * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(a.data(), b->d.hist[b->h], sizeof(HRec) * K * N, hipMemcpyDeviceToHost));
   HIPTRY(hipMemcpy(wa.data(), b->d.wA[b->h], sizeof(float4) * b->max_walls * N, hipMemcpyDeviceToHost));
   HIPTRY(hipMemcpy(wc.data(), b->d.wB[b->h], sizeof(float2) * b->max_walls * N, hipMemcpyDeviceToHost));
   std::vector<lpr_history> recs;
@@ -878,9 +873,8 @@ static lpr_status get_history_impl(lpr_bed* b, int32_t bed, lpr_history* out, in
     if (sid[i] < 0) continue;
     for (int k = 0; k < cnt[i]; ++k)
       if ((fl[i] >> k) & 1u) {
-        const float4 A = a[(size_t)k * N + i];
-        const float2 C = c[(size_t)k * N + i];
-        recs.push_back({sid[i], sid[idx[(size_t)k * N + i]], {A.x, A.y, A.z}, {A.w, C.x, C.y}});
+        const HRec& A = a[(size_t)k * N + i];
+        recs.push_back({sid[i], sid[idx[(size_t)k * N + i]], {A.t.x, A.t.y, A.t.z}, {A.r.x, A.r.y, A.r.z}});
       }
     for (int w = 0; w < H.nwall; ++w)
       if ((fl[i] >> (WALL_BIT + w)) & 1u) {
@@ -916,17 +910,36 @@ static lpr_status set_history_impl(lpr_bed* b, int32_t bed, const lpr_history* r
     if (rec[q].owner < 0 || rec[q].owner >= H.n) return fail(LPR_E_INVAL, "history owner out of range");
     by_owner[rec[q].owner].push_back(&rec[q]);
   }
-  std::vector<uint32_t> fl(N, 0u);
-  std::vector<float4> a((size_t)K * N, make_float4(0, 0, 0, 0)), wa((size_t)b->max_walls * N, make_float4(0, 0, 0, 0));
-  std::vector<float2> c((size_t)K * N, make_float2(0, 0)), wc((size_t)b->max_walls * N, make_float2(0, 0));
+  // the other beds of a batch keep their records: start from the device
+  // arrays and clear this bed's range
+  const int W = b->max_walls;
+  std::vector<uint32_t> fl(N);
+  std::vector<HRec> a((size_t)K * N);
+  std::vector<float4> wa((size_t)W * N);
+  std::vector<float2> wc((size_t)W * N);
+  HIPTRY(hipMemcpy(fl.data(), b->d.cflag[b->h], sizeof(uint32_t) * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(a.data(), b->d.hist[b->h], sizeof(HRec) * K * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(wa.data(), b->d.wA[b->h], sizeof(float4) * W * N, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(wc.data(), b->d.wB[b->h], sizeof(float2) * W * N, hipMemcpyDeviceToHost));
+  for (int64_t i = H.p0; i < H.p0 + H.npad; ++i) {
+    fl[i] = 0u;
+    for (int k = 0; k < K; ++k) {
+      a[(size_t)k * N + i].t = make_float4(0, 0, 0, 0);
+      a[(size_t)k * N + i].r = make_float4(0, 0, 0, 0);
+    }
+    for (int w = 0; w < W; ++w) {
+      wa[(size_t)w * N + i] = make_float4(0, 0, 0, 0);
+      wc[(size_t)w * N + i] = make_float2(0, 0);
+    }
+  }
   for (int64_t i = H.p0; i < H.p0 + H.npad; ++i) {
     if (sid[i] < 0) continue;
     for (const lpr_history* r : by_owner[sid[i]]) {
       if (r->partner >= 0) {
         for (int k = 0; k < cnt[i]; ++k)
           if (sid[idx[(size_t)k * N + i]] == r->partner) {
-            a[(size_t)k * N + i] = make_float4(r->xi_t[0], r->xi_t[1], r->xi_t[2], r->xi_r[0]);
-            c[(size_t)k * N + i] = make_float2(r->xi_r[1], r->xi_r[2]);
+            a[(size_t)k * N + i].t = make_float4(r->xi_t[0], r->xi_t[1], r->xi_t[2], 0.f);
+            a[(size_t)k * N + i].r = make_float4(r->xi_r[0], r->xi_r[1], r->xi_r[2], 0.f);
             fl[i] |= 1u << k;
           }
       } else {
@@ -940,10 +953,9 @@ static lpr_status set_history_impl(lpr_bed* b, int32_t bed, const lpr_history* r
     }
   }
   HIPTRY(hipMemcpy(b->d.cflag[b->h], fl.data(), sizeof(uint32_t) * N, hipMemcpyHostToDevice));
-  HIPTRY(hipMemcpy(b->d.hA[b->h], a.data(), sizeof(float4) * K * N, hipMemcpyHostToDevice));
-  HIPTRY(hipMemcpy(b->d.hB[b->h], c.data(), sizeof(float2) * K * N, hipMemcpyHostToDevice));
-  HIPTRY(hipMemcpy(b->d.wA[b->h], wa.data(), sizeof(float4) * b->max_walls * N, hipMemcpyHostToDevice));
-  HIPTRY(hipMemcpy(b->d.wB[b->h], wc.data(), sizeof(float2) * b->max_walls * N, hipMemcpyHostToDevice));
+  HIPTRY(hipMemcpy(b->d.hist[b->h], a.data(), sizeof(HRec) * K * N, hipMemcpyHostToDevice));
+  HIPTRY(hipMemcpy(b->d.wA[b->h], wa.data(), sizeof(float4) * W * N, hipMemcpyHostToDevice));
+  HIPTRY(hipMemcpy(b->d.wB[b->h], wc.data(), sizeof(float2) * W * N, hipMemcpyHostToDevice));
   return LPR_OK;
 }
 
@@ -1250,9 +1262,8 @@ bool adj_reserve(lpr_bed* b, int steps, int nckpt) {
   const int W = b->max_walls;
   AdjBufs& a = b->adj;
   if (b->adj_steps < steps) {
-    bool ok = dal(b, &a.pos, (size_t)steps * N) && dal(b, &a.vel, (size_t)steps * N) &&
-              dal(b, &a.omg, (size_t)steps * N) && dal(b, &a.cflag, (size_t)steps * N) &&
-              dal(b, &a.hA, (size_t)steps * K * N) && dal(b, &a.hB, (size_t)steps * K * N) &&
+    bool ok = dal(b, &a.st, (size_t)steps * N) && dal(b, &a.cflag, (size_t)steps * N) &&
+              dal(b, &a.hist, (size_t)steps * K * N) &&
               dal(b, &a.wA, (size_t)steps * W * N) && dal(b, &a.wB, (size_t)steps * W * N);
     const int nw = std::max(1, (int)(b->hb.back().wall0 + b->hb.back().nwall));
     ok = ok && dal(b, &a.walls, (size_t)steps * nw);
@@ -1273,8 +1284,8 @@ bool adj_reserve(lpr_bed* b, int steps, int nckpt) {
   while ((int)b->ckpts.size() < nckpt) {
     lpr_bed::Ckpt c{};
     const size_t nb = std::max<size_t>(1, b->hb.back().body0 + b->hb.back().nbody);
-    bool ok = dal(b, &c.pos, N) && dal(b, &c.vel, N) && dal(b, &c.omg, N) && dal(b, &c.cflag, N) &&
-              dal(b, &c.hA, (size_t)K * N) && dal(b, &c.hB, (size_t)K * N) && dal(b, &c.wA, (size_t)W * N) &&
+    bool ok = dal(b, &c.st, N) && dal(b, &c.cflag, N) &&
+              dal(b, &c.hist, (size_t)K * N) && dal(b, &c.wA, (size_t)W * N) &&
               dal(b, &c.wB, (size_t)W * N) && dal(b, &c.own_cnt, N) && dal(b, &c.own_idx, (size_t)K * N) &&
               dal(b, &c.bedyn, b->hb.size()) && dal(b, &c.bdyn, nb);
     if (!ok) return false;
@@ -1293,12 +1304,9 @@ lpr_status ckpt_save(lpr_bed* b, lpr_bed::Ckpt& c) {
   const int W = b->max_walls;
   const size_t nb = std::max<size_t>(1, b->hb.back().body0 + b->hb.back().nbody);
   hipStream_t st = b->stream;
-  HIPTRY(d2d(c.pos, d.pos[b->s], sizeof(double4) * N, st));
-  HIPTRY(d2d(c.vel, d.vel[b->s], sizeof(float4) * N, st));
-  HIPTRY(d2d(c.omg, d.omg[b->s], sizeof(float4) * N, st));
+  HIPTRY(d2d(c.st, d.st[b->s], sizeof(PState) * N, st));
   HIPTRY(d2d(c.cflag, d.cflag[b->h], sizeof(uint32_t) * N, st));
-  HIPTRY(d2d(c.hA, d.hA[b->h], sizeof(float4) * K * N, st));
-  HIPTRY(d2d(c.hB, d.hB[b->h], sizeof(float2) * K * N, st));
+  HIPTRY(d2d(c.hist, d.hist[b->h], sizeof(HRec) * K * N, st));
   HIPTRY(d2d(c.wA, d.wA[b->h], sizeof(float4) * W * N, st));
   HIPTRY(d2d(c.wB, d.wB[b->h], sizeof(float2) * W * N, st));
   HIPTRY(d2d(c.own_cnt, d.own_cnt[b->l], sizeof(int32_t) * N, st));
@@ -1318,12 +1326,9 @@ lpr_status ckpt_restore(lpr_bed* b, const lpr_bed::Ckpt& c) {
   hipStream_t st = b->stream;
   b->s = c.s; b->h = c.h; b->l = c.l;
   b->since = c.since; b->host_steps = c.host_steps; b->rebuilds = c.rebuilds;
-  HIPTRY(d2d(d.pos[b->s], c.pos, sizeof(double4) * N, st));
-  HIPTRY(d2d(d.vel[b->s], c.vel, sizeof(float4) * N, st));
-  HIPTRY(d2d(d.omg[b->s], c.omg, sizeof(float4) * N, st));
+  HIPTRY(d2d(d.st[b->s], c.st, sizeof(PState) * N, st));
   HIPTRY(d2d(d.cflag[b->h], c.cflag, sizeof(uint32_t) * N, st));
-  HIPTRY(d2d(d.hA[b->h], c.hA, sizeof(float4) * K * N, st));
-  HIPTRY(d2d(d.hB[b->h], c.hB, sizeof(float2) * K * N, st));
+  HIPTRY(d2d(d.hist[b->h], c.hist, sizeof(HRec) * K * N, st));
   HIPTRY(d2d(d.wA[b->h], c.wA, sizeof(float4) * W * N, st));
   HIPTRY(d2d(d.wB[b->h], c.wB, sizeof(float2) * W * N, st));
   HIPTRY(d2d(d.own_cnt[b->l], c.own_cnt, sizeof(int32_t) * N, st));
@@ -1472,12 +1477,9 @@ lpr_status lpr_adjoint_window(lpr_bed* b, int64_t n_steps, int32_t ckpt_every, i
         HIPTRY(d2d(a.rev_start, d.rev_start, sizeof(uint32_t) * (N + 1), sm));
         HIPTRY(d2d(a.rev_ent, d.rev_ent, sizeof(uint32_t) * K * N, sm));
       }
-      HIPTRY(d2d(a.pos + (int64_t)q * N, d.pos[b->s], sizeof(double4) * N, sm));
-      HIPTRY(d2d(a.vel + (int64_t)q * N, d.vel[b->s], sizeof(float4) * N, sm));
-      HIPTRY(d2d(a.omg + (int64_t)q * N, d.omg[b->s], sizeof(float4) * N, sm));
+      HIPTRY(d2d(a.st + (int64_t)q * N, d.st[b->s], sizeof(PState) * N, sm));
       HIPTRY(d2d(a.cflag + (int64_t)q * N, d.cflag[b->h], sizeof(uint32_t) * N, sm));
-      HIPTRY(d2d(a.hA + (int64_t)q * K * N, d.hA[b->h], sizeof(float4) * K * N, sm));
-      HIPTRY(d2d(a.hB + (int64_t)q * K * N, d.hB[b->h], sizeof(float2) * K * N, sm));
+      HIPTRY(d2d(a.hist + (int64_t)q * K * N, d.hist[b->h], sizeof(HRec) * K * N, sm));
       HIPTRY(d2d(a.wA + (int64_t)q * W * N, d.wA[b->h], sizeof(float4) * W * N, sm));
       HIPTRY(d2d(a.wB + (int64_t)q * W * N, d.wB[b->h], sizeof(float2) * W * N, sm));
       HIPTRY(d2d(a.walls + (int64_t)q * a.nwall_total, d.walls, sizeof(WallPose) * a.nwall_total, sm));
