@@ -29,6 +29,14 @@ struct PState {
   float4 w;   // angular velocity, 1/I
 };
 
+// A search candidate in cell-list order: position (FP64), radius (the FP32
+// value it was created with) and stable id, 32 bytes read as one.
+struct CRec {
+  double x, y, z;
+  float r;
+  int32_t sid;
+};
+
 // Spring history of one contact slot, 32 bytes so that the partner side of
 // a contact reads it as one sector.
 struct HRec {

@@ -43,8 +43,8 @@ struct DevBufs {
   int64_t nblk;          // blocks of the smallest step-kernel block size (N / 64)
   // scan scratch
   uint32_t* scan_tmp;
-  double4* cpos;         // position and radius in cell-list order (rebuild)
-  int32_t* csid;         // stable id in cell-list order (rebuild)
+  CRec* crec;            // position, radius and stable id in cell-list order (rebuild)
+  float4* cpf;           // FP32 (x, y, z, r) in cell-list order (rebuild)
   int32_t* zext;         // [levels][2] occupied z-row range (monotone)
   float* disp;           // distance bound moved since the last rebuild
   uint32_t* viol;        // [2] skin-exceeded flags, by state parity

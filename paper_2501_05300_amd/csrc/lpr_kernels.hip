@@ -126,8 +126,15 @@ __global__ void k_scatter(DevBufs d, int s) {
   const int32_t c = d.pcell[i];
   const uint32_t q = d.cell_start[c] + d.prank[i];
   d.cell_list[q] = (int32_t)i;
-  d.cpos[q] = d.st[s][i].x;
-  d.csid[q] = d.sid[i];
+  const double4 p = d.st[s][i].x;
+  CRec cr;
+  cr.x = p.x;
+  cr.y = p.y;
+  cr.z = p.z;
+  cr.r = (float)p.w;  // radii are FP32 values, so this is exact
+  cr.sid = d.sid[i];
+  d.crec[q] = cr;
+  d.cpf[q] = make_float4((float)p.x, (float)p.y, (float)p.z, (float)p.w);
 }
 
 void launch_scatter(const DevBufs& d, int s, hipStream_t st) {
@@ -223,15 +230,17 @@ void launch_scan(uint32_t* cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipSt
 // level and every coarser one (a coarser level only when its occupied rows
 // reach the particle's row).  The neighbourhood is at most 3 x 3 rows of up
 // to 3 cells; the cells of a row are consecutive in the cell order, so the
-// row is one range of the cell lists (two where the x axis wraps), and the
-// cell-ordered copies of position, radius and stable id make each range one
-// contiguous read.  All 18 range bounds are loaded before the first
-// candidate, so no candidate read waits on an index read.  The exact FP64
-// predicate runs on every candidate the owner rule keeps; accepted partners
-// collect in LDS, are put in ascending stable id, and inherit their spring
-// history from the previous lists.
+// row is one range of the cell lists (two where the x axis wraps).  All 18
+// range bounds are loaded before the first candidate.  A first pass reads
+// the 16-byte FP32 copy of each candidate, four per round, and keeps the
+// ones within a conservative FP32 distance bound (and not owned by the
+// partner); a second pass reads the kept candidates' FP64 records, four at a
+// time, and applies the owner rule and the exact predicate.  Accepted
+// partners are put in ascending stable id and inherit their spring history
+// from the previous lists.
 
-constexpr int SBS = 64;  // threads per search block
+constexpr int SBS = 64;   // threads per search block
+constexpr int PCAP = 24;  // first-pass candidates kept per particle
 
 // Cell ranges [xa, xb) along x covering cx - 1 .. cx + 1 (two pieces where a
 // periodic axis wraps; the whole axis when it has three cells or fewer).
@@ -262,9 +271,41 @@ LPR_DEV_INLINE int x_pieces(const LevelGrid& G, int cx, int xa[2], int xb[2]) {
   return 1;
 }
 
+// Cell-list bounds of the particle's neighbour rows at one level.
+LPR_DEV_INLINE void row_bounds(const DevBufs& d, const LevelGrid& G, const double4& pi, uint32_t q0[18],
+                               uint32_t q1[18]) {
+  int ly[3], lz[3], xa[2], xb[2];
+  const int nyl = axis_neighbours(G, 1, cell_axis(G, 1, pi.y), ly);
+  const int nzl = axis_neighbours(G, 2, cell_axis(G, 2, pi.z), lz);
+  const int nxp = x_pieces(G, cell_axis(G, 0, pi.x), xa, xb);
+#pragma unroll
+  for (int r = 0; r < 18; ++r) {
+    const int a = r / 6, b = (r / 2) % 3, p = r & 1;
+    q0[r] = 0u;
+    q1[r] = 0u;
+    if (a < nzl && b < nyl && p < nxp) {
+      const int64_t rb = G.base + ((int64_t)lz[a] * G.n[1] + ly[b]) * G.n[0];
+      q0[r] = d.cell_start[rb + xa[p]];
+      q1[r] = d.cell_start[rb + xb[p]];
+    }
+  }
+}
+
+// Owner rule (the smaller radius owns; equal radii, the smaller stable id)
+// and the exact FP64 predicate d < r_i + r_j + skin.
+LPR_DEV_INLINE bool owner_candidate(const BedConst& bc, const double4& pi, int32_t si, double skin, const CRec& c) {
+  const float rif = (float)pi.w;
+  if (c.r < rif) return false;
+  if (c.r == rif && c.sid <= si) return false;
+  const double4 pj = make_double4(c.x, c.y, c.z, (double)c.r);
+  double dx, dy, dz;
+  const double d2 = pair_sep(bc, pi, pj, dx, dy, dz);
+  return within_skin(d2, pi.w, pj.w, skin);
+}
+
 __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho) {
   __shared__ int32_t c_sid[K][SBS];
-  __shared__ int32_t c_idx[K][SBS];
+  __shared__ int32_t c_idx[PCAP][SBS];  // kept candidates, then the accepted ones
   const int t = threadIdx.x;
   // each XCD takes one contiguous range of particles, so the neighbour rows
   // its blocks read overlap in that XCD's L2
@@ -290,7 +331,16 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
   const float rif = (float)pi.w;
   const int32_t si = d.sid[i];
   const double skin = (double)bc.skin;
-  int cnt = 0;
+  const float pfx = (float)pi.x, pfy = (float)pi.y, pfz = (float)pi.z;
+  const float Lx = (float)bc.L[0], Ly = (float)bc.L[1];
+  const bool perx = (bc.periodic & 1u) != 0, pery = (bc.periodic & 2u) != 0;
+  // FP32 bound: rounding the coordinates to FP32 and forming their (wrapped)
+  // differences errs by a few ulp of the largest magnitude involved (the
+  // candidate lies within the particle's magnitude plus one period);
+  // 2^-19 of it is 16 ulp
+  const float mag = fmaxf(fmaxf(fabsf(pfx), fabsf(pfy)), fmaxf(fabsf(pfz), fmaxf(Lx, Ly)));
+  const float reach = rif + bc.skin + mag * 0x1p-19f;
+  int np = 0;
   for (int lev = lev_i; lev < bc.nlev; ++lev) {
     const int gl = bc.lev0 + lev;
     const LevelGrid G = d.levels[gl];
@@ -300,54 +350,74 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
       const int zu = row_unclamped(G, pi.z);
       if (zu < d.zext[2 * gl] - 1 || zu > d.zext[2 * gl + 1] + 1) continue;
     }
-    int ly[3], lz[3], xa[2], xb[2];
-    const int nyl = axis_neighbours(G, 1, cell_axis(G, 1, pi.y), ly);
-    const int nzl = axis_neighbours(G, 2, cell_axis(G, 2, pi.z), lz);
-    const int nxp = x_pieces(G, cell_axis(G, 0, pi.x), xa, xb);
-    // every range bound first
     uint32_t q0[18], q1[18];
+    row_bounds(d, G, pi, q0, q1);
 #pragma unroll
     for (int r = 0; r < 18; ++r) {
-      const int a = r / 6, b = (r / 2) % 3, p = r & 1;
-      q0[r] = 0u;
-      q1[r] = 0u;
-      if (a < nzl && b < nyl && p < nxp) {
-        const int64_t rb = G.base + ((int64_t)lz[a] * G.n[1] + ly[b]) * G.n[0];
-        q0[r] = d.cell_start[rb + xa[p]];
-        q1[r] = d.cell_start[rb + xb[p]];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 18; ++r) {
-      // four candidates per round, their reads issued together
       for (uint32_t q = q0[r]; q < q1[r]; q += 4) {
-        double4 pj[4];
-        int32_t sj[4];
+        float4 c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = d.cpf[(q + u < q1[r]) ? q + u : q];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const uint32_t qq = (q + u < q1[r]) ? q + u : q;
-          pj[u] = d.cpos[qq];
-          sj[u] = d.csid[qq];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (q + u >= q1[r]) break;
-          const float rjf = (float)pj[u].w;
-          if (rjf < rif) continue;  // j owns the pair
-          if (rjf == rif && sj[u] <= si) continue;  // equal radii: smaller id owns (and not itself)
-          double dx, dy, dz;
-          const double d2 = pair_sep(bc, pi, pj[u], dx, dy, dz);
-          if (within_skin(d2, pi.w, pj[u].w, skin)) {
-            if (cnt < K) {
-              c_sid[cnt][t] = sj[u];
-              c_idx[cnt][t] = (int32_t)(q + u);
-            }
-            ++cnt;
+          if (q + u >= q1[r] || c[u].w < rif) continue;  // j owns pairs with a smaller radius
+          float fx = c[u].x - pfx, fy = c[u].y - pfy;
+          const float fz = c[u].z - pfz;
+          if (perx) fx = (fx > 0.5f * Lx) ? fx - Lx : ((fx < -0.5f * Lx) ? fx + Lx : fx);
+          if (pery) fy = (fy > 0.5f * Ly) ? fy - Ly : ((fy < -0.5f * Ly) ? fy + Ly : fy);
+          const float Rf = reach + c[u].w;
+          if (fx * fx + fy * fy + fz * fz < Rf * Rf) {
+            if (np < PCAP) c_idx[np][t] = (int32_t)(q + u);
+            ++np;
           }
         }
       }
     }
   }
+  if (np > PCAP) {
+    // more kept candidates than the list holds: exact walk from the FP64
+    // records (a dense cluster; the capacity check below still applies)
+    np = 0;
+    for (int lev = lev_i; lev < bc.nlev; ++lev) {
+      const int gl = bc.lev0 + lev;
+      const LevelGrid G = d.levels[gl];
+      if (lev > lev_i) {
+        const int zu = row_unclamped(G, pi.z);
+        if (zu < d.zext[2 * gl] - 1 || zu > d.zext[2 * gl + 1] + 1) continue;
+      }
+      uint32_t q0[18], q1[18];
+      row_bounds(d, G, pi, q0, q1);
+      for (int r = 0; r < 18; ++r)
+        for (uint32_t q = q0[r]; q < q1[r]; ++q)
+          if (owner_candidate(bc, pi, si, skin, d.crec[q])) {
+            if (np < PCAP) c_idx[np][t] = (int32_t)q;
+            ++np;
+          }
+    }
+  }
+  // exact pass over the kept candidates, reads four at a time; accepted ones
+  // are compacted in place
+  int cnt = 0;
+  const int nk = min(np, PCAP);
+  for (int a = 0; a < nk; a += 4) {
+    CRec c[4];
+    int32_t qv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      qv[u] = c_idx[(a + u < nk) ? a + u : a][t];
+      c[u] = d.crec[qv[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (a + u < nk && owner_candidate(bc, pi, si, skin, c[u])) {
+        if (cnt < K) {
+          c_idx[cnt][t] = qv[u];
+          c_sid[cnt][t] = c[u].sid;
+        }
+        ++cnt;
+      }
+  }
+  if (np > PCAP) cnt = max(cnt, K + 1);  // more partners than slots
   if (cnt > K) {
     atomicOr(d.err, ERR_CAPACITY);
     cnt = K;
@@ -490,22 +560,46 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
     const int n_own = d.own_cnt[l][i];
     const uint32_t rs = d.rev_start[i];
     const int n_tot = n_own + (int)(d.rev_start[i + 1] - rs);
-    for (int e = 0; e < n_tot; ++e) {
-      int64_t o, q;
-      int k;
-      const bool mine = e < n_own;
-      if (mine) {
-        k = e;
-        o = i;
-        q = d.own_idx[l][k * N + i];
+    // contact e + 1's partner state and history are read while contact e is
+    // evaluated
+    int64_t o_n = 0, oth_n = 0;
+    int k_n = 0;
+    PState ot_n{};
+    HRec hr_n{};
+    if (n_tot > 0) {
+      if (n_own > 0) {
+        k_n = 0;
+        o_n = i;
+        oth_n = d.own_idx[l][i];
       } else {
-        const uint32_t pk = d.rev_ent[rs + (e - n_own)];
-        o = pk >> 4;
-        k = (int)(pk & 15u);
-        q = i;
+        const uint32_t pk = d.rev_ent[rs];
+        o_n = pk >> 4;
+        k_n = (int)(pk & 15u);
+        oth_n = o_n;
       }
-      const int64_t other = mine ? q : o;
-      const PState ot = d.st[s][other];
+      ot_n = d.st[s][oth_n];
+      hr_n = d.hist[h][k_n * N + o_n];
+    }
+    for (int e = 0; e < n_tot; ++e) {
+      const int64_t o = o_n;
+      const int k = k_n;
+      const PState ot = ot_n;
+      const HRec hr_pf = hr_n;
+      const bool mine = e < n_own;
+      if (e + 1 < n_tot) {
+        if (e + 1 < n_own) {
+          k_n = e + 1;
+          o_n = i;
+          oth_n = d.own_idx[l][(int64_t)k_n * N + i];
+        } else {
+          const uint32_t pk = d.rev_ent[rs + (e + 1 - n_own)];
+          o_n = pk >> 4;
+          k_n = (int)(pk & 15u);
+          oth_n = o_n;
+        }
+        ot_n = d.st[s][oth_n];
+        hr_n = d.hist[h][k_n * N + o_n];
+      }
       const double4 xo_ = ot.x;
       const float4 vo_ = ot.v;
       const float4 wo_ = ot.w;
@@ -526,7 +620,7 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
       // slots out of contact hold zeros, so the history is read as it is
       LawIn in;
       {
-        const HRec hr = d.hist[h][k * N + o];
+        const HRec hr = hr_pf;
         in.xt = f3(hr.t.x, hr.t.y, hr.t.z);
         in.xr = f3(hr.r.x, hr.r.y, hr.r.z);
       }

@@ -537,7 +537,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   ok &= dal(b, &d.sid, N) && dal(b, &d.meta, N) && dal(b, &d.chunk_bed32, N / PAD);
   ok &= dal(b, &d.cell_cnt, cell_base) && dal(b, &d.cell_start, cell_base + 1);
   ok &= dal(b, &d.pcell, N) && dal(b, &d.prank, N) && dal(b, &d.cell_list, N);
-  ok &= dal(b, &d.cpos, N) && dal(b, &d.csid, N) && dal(b, &d.zext, 2 * levels.size());
+  ok &= dal(b, &d.crec, N) && dal(b, &d.cpf, N) && dal(b, &d.zext, 2 * levels.size());
   ok &= dal(b, &d.disp, N) && dal(b, &d.viol, 2);
   ok &= dal(b, &d.own_rank, (size_t)K * N) && dal(b, &d.rev_cnt, N) && dal(b, &d.rev_start, N + 1);
   ok &= dal(b, &d.rev_ent, (size_t)K * N);
