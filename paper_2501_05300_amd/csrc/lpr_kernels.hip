@@ -95,6 +95,8 @@ LPR_DEV_INLINE int row_unclamped(const LevelGrid& G, double z) {
 
 // Bins every particle into the grid of its own level and widens the level's
 // occupied z-row range (monotone, so a stale range is still a superset).
+// Consecutive particles mostly share cells: the lanes of a wave that fall in
+// one cell take their ranks from a single atomic (ballot, prefix count).
 __global__ void k_bin(DevBufs d, int s) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= d.N || latched(d.err)) return;
@@ -107,7 +109,20 @@ __global__ void k_bin(DevBufs d, int s) {
   const int cx = cell_axis(G, 0, p.x), cy = cell_axis(G, 1, p.y), cz = cell_axis(G, 2, p.z);
   const int32_t c = (int32_t)(G.base + ((int64_t)cz * G.n[1] + cy) * G.n[0] + cx);
   d.pcell[i] = c;
-  d.prank[i] = atomicAdd(&d.cell_cnt[c], 1u);
+  const int lane = (int)(threadIdx.x & 63u);
+  uint64_t todo = __ballot(1);  // the wave's active lanes
+  uint32_t rank = 0u;
+  while (todo != 0ull) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const int32_t key = __shfl(c, leader, 64);
+    const uint64_t grp = __ballot(c == key) & todo;
+    uint32_t base = 0u;
+    if (lane == leader) base = atomicAdd(&d.cell_cnt[key], (uint32_t)__popcll(grp));
+    base = __shfl(base, leader, 64);
+    if ((grp >> lane) & 1ull) rank = base + (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
+    todo &= ~grp;
+  }
+  d.prank[i] = rank;
   const int zu = row_unclamped(G, p.z);
   if (zu < *(const volatile int*)&d.zext[2 * gl]) atomicMin(&d.zext[2 * gl], zu);
   if (zu > *(const volatile int*)&d.zext[2 * gl + 1]) atomicMax(&d.zext[2 * gl + 1], zu);
@@ -232,7 +247,7 @@ void launch_scan(uint32_t* cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipSt
 // to 3 cells; the cells of a row are consecutive in the cell order, so the
 // row is one range of the cell lists (two where the x axis wraps).  All 18
 // range bounds are loaded before the first candidate.  A first pass reads
-// the 16-byte FP32 copy of each candidate, four per round, and keeps the
+// the 16-byte FP32 copy of each candidate, eight per round, and keeps the
 // ones within a conservative FP32 distance bound (and not owned by the
 // partner); a second pass reads the kept candidates' FP64 records, four at a
 // time, and applies the owner rule and the exact predicate.  Accepted
@@ -354,12 +369,12 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
     row_bounds(d, G, pi, q0, q1);
 #pragma unroll
     for (int r = 0; r < 18; ++r) {
-      for (uint32_t q = q0[r]; q < q1[r]; q += 4) {
-        float4 c[4];
+      for (uint32_t q = q0[r]; q < q1[r]; q += 8) {
+        float4 c[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) c[u] = d.cpf[(q + u < q1[r]) ? q + u : q];
+        for (int u = 0; u < 8; ++u) c[u] = d.cpf[(q + u < q1[r]) ? q + u : q];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
           if (q + u >= q1[r] || c[u].w < rif) continue;  // j owns pairs with a smaller radius
           float fx = c[u].x - pfx, fy = c[u].y - pfy;
           const float fz = c[u].z - pfz;
