@@ -18,7 +18,6 @@ every k steps (the contact set found each step is the same).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -41,25 +40,19 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("lpr_dev.h", "lpr_kernels.hip"):
-        with open(os.path.join(ROOT, "paper_2501_05300_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def counter_traffic(n_particles):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
-    counter summary, when it was taken on the current kernel source."""
+    """HBM bytes per launch of the step kernel (every-step search, skin lists)
+    from the committed rocprofv3 counter record, when it was taken on the
+    current kernel source; otherwise (None, None)."""
+    from paper_2501_05300_amd.profile_summary import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "step_kernel_counters_metric_bed.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     with open(path) as f:
         c = json.load(f)
     if c.get("kernel_source_hash") != kernel_source_hash() or c.get("n") != n_particles:
-        return None
-    return c.get("hbm_bytes_per_launch")
+        return None, None
+    return c.get("hbm_bytes_per_launch"), c.get("hbm_bytes_per_launch_skin_lists")
 
 
 def settle_beds(specs, steps, chunk=5000):
@@ -154,7 +147,8 @@ def batch_leg(steps, warmup, settle, tune_steps):
 
 def adjoint_leg(n, window, ckpt, settle, pre, seed=0):
     """Adjoint form on the 50k-sphere graded bed (r0 1.5 mm, L 20 mm, k 1,
-    0.2 m deep) under a 0.1 m plate pushed at 0.01 m/s: one reverse-mode
+    0.2 m deep) under a 0.1 m plate pushed at 0.01 m/s (`pre` steps first, so
+    that the plate is loaded: 50,000 steps sink it 1 mm): one reverse-mode
     window of `window` steps with a checkpoint every `ckpt` steps, timed
     against the same steps run forward only from the same state."""
     import torch
@@ -168,8 +162,13 @@ def adjoint_leg(n, window, ckpt, settle, pre, seed=0):
     body = spec.info["plate_body"]
     skin = 0.25 * float(spec.radius.min())
     bed = Bed(spec, rebuild_every=10, skin=skin)
-    bed.step(pre)
-    bed.sync()
+    done = 0
+    while done < pre:
+        k = min(10_000, pre - done)
+        bed.step(k)
+        bed.sync()
+        done += k
+    log(f"adjoint bed: plate pushed {pre} steps")
     x, v, w = bed.state()
     keys, vals = bed.history()
     clock = bed.clock()
@@ -289,7 +288,7 @@ def main():
     step_ms = prof["step"] / args.steps
     b_alg = B_PARTICLE + B_PAIR * cbar
     achieved = N * b_alg / (step_ms * 1e-3) / 1e9
-    traffic = counter_traffic(N)
+    traffic, traffic_skin = counter_traffic(N)
     out = {
         "metric": METRIC,
         "value": value,
@@ -312,8 +311,10 @@ def main():
         "kernel_ms_per_step": {k: v / args.steps for k, v in prof.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_GBs": traffic / (step_ms * 1e-3) / 1e9 if traffic else None,
+                     "traffic_frac": traffic / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
                      "kernel": "k_step (fused narrow phase, law, accumulation, walls, integration)",
-                     "bytes_per_particle_step": b_alg},
+                     "bytes_per_particle_step": b_alg, "algorithmic_bytes_per_launch": N * b_alg},
         "algorithmic_frac_whole_step": N * b_alg / (wall / args.steps) / 1e9 / HBM_PEAK_GBS,
     }
     if args.secondary_every > 1:
@@ -339,6 +340,9 @@ def main():
             "kernel_ms_per_step": {k: v / args.steps for k, v in prof2.items()},
             "step_kernel_achieved_GBs": N * b2 / (step2 * 1e-3) / 1e9,
             "step_kernel_frac": N * b2 / (step2 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "step_kernel_traffic": traffic_skin,
+            "step_kernel_traffic_frac": traffic_skin / (step2 * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic_skin else None,
+            "algorithmic_frac_whole_step": N * b2 / (wall2 / args.steps) / 1e9 / HBM_PEAK_GBS,
         }
     if args.cpu_steps > 0:
         pos, vel, omg = bed.state()
@@ -351,7 +355,7 @@ def main():
     if args.batch_steps > 0:
         out["batched"] = batch_leg(args.batch_steps, 100, args.batch_settle, 10)
     if args.adjoint_window > 0:
-        out["adjoint"] = adjoint_leg(50_000, args.adjoint_window, 100, args.settle, 5000, args.seed)
+        out["adjoint"] = adjoint_leg(50_000, args.adjoint_window, 100, args.settle, 50_000, args.seed)
     print(json.dumps(out), flush=True)
 
 
