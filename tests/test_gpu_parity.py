@@ -203,3 +203,32 @@ def test_grousered_ring_parity():
         bed.step(100)
     n_ring = int(np.sum(bed.contacts()[:, 1] <= -2))
     assert n_ring > 0
+
+
+def test_full_size_graded_bed_step_parity():
+    """The 2,000,000-sphere graded bed the throughput is measured on, in the
+    launch configuration the bench times (cell search every step, 256-thread
+    step blocks): relaxed on the GPU until contacts form, then one step
+    against the oracle on the same state. Contact lists equal, forces and
+    torques within 1e-5."""
+    from paper_2501_05300_amd.lprdem import Bed
+    spec = beds.metric_bed()
+    relax = spec.copy()
+    relax.params = beds.settle_params(spec.params).replace(dt=5e-6, gamma_factor=10.0)
+    for w in relax.walls:
+        w.mu_t, w.mu_r = 0.0, 0.0
+    rb = Bed(relax, rebuild_every=5, skin=0.25 * float(spec.radius.min()))
+    for _ in range(6):
+        rb.step(5000)
+        rb.sync()
+    x, _, _ = rb.state()
+    rb.close()
+    spec.pos = x
+    bed = gpu_bed(spec)
+    bed.step(3)
+    res = compare_one_step(spec, bed)
+    print({k: v for k, v in res.items() if k not in ("only_gpu", "only_oracle")})
+    assert res["contacts_equal"], res
+    assert res["n_contacts"] > spec.n  # a bed in contact, not a falling cloud
+    assert res["force_rel"] < FTOL and res["torque_rel"] < FTOL
+    assert res["reaction0_rel"] < FTOL
