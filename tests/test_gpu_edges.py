@@ -1,0 +1,105 @@
+"""Edge cases of the HIP stepper: a lone sphere, rejected descriptions, a
+particle with more partners than slots, coincident spheres (GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2501_05300_amd import beds
+from parity_util import compare_one_step
+
+pytestmark = pytest.mark.gpu
+
+
+def spec_of(pos, radius, box=(0.1, 0.1, 0.0), periodic=3, params=None, walls=None, bodies=None):
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    n = pos.shape[0]
+    return beds.BedSpec(pos=pos, radius=np.asarray(radius, np.float32).reshape(n), vel=np.zeros((n, 3), np.float32),
+                        omega=np.zeros((n, 3), np.float32), box=box, periodic=periodic,
+                        params=params if params is not None else beds.paper_params(), walls=walls or [],
+                        bodies=bodies or [beds.Body()])
+
+
+def test_lone_sphere_falls_freely():
+    """No contacts: velocity-then-position Euler gives v_k = k dt g and
+    z_k = z_0 + dt^2 g k (k + 1) / 2 (FP32 velocity, FP64 position)."""
+    from paper_2501_05300_amd.lprdem import Bed
+    spec = spec_of([[0.05, 0.05, 0.5]], [2e-3])
+    bed = Bed(spec)
+    k = 1000
+    bed.step(k)
+    x, v, _ = bed.state()
+    dt, g = spec.params.dt, spec.params.g[2]
+    vz = k * dt * g
+    dz = dt * dt * g * k * (k + 1) / 2
+    assert abs(v[0, 2] - vz) <= 1e-4 * abs(vz)  # k FP32 additions
+    assert abs((x[0, 2] - 0.5) - dz) <= 1e-4 * abs(dz)
+    assert x[0, 0] == 0.05 and x[0, 1] == 0.05
+    assert bed.contacts().shape[0] == 0
+
+
+@pytest.mark.parametrize("case", ["empty", "negative_radius", "nan_position", "short_period", "cadence_without_skin",
+                                  "band_ratio", "block"])
+def test_invalid_descriptions_are_rejected(case):
+    from paper_2501_05300_amd.lprdem import Bed, LprError
+    kw = {}
+    spec = spec_of([[0.05, 0.05, 0.01], [0.06, 0.05, 0.01]], [2e-3, 2e-3])
+    if case == "empty":
+        spec = spec_of(np.zeros((0, 3)), np.zeros(0))
+    elif case == "negative_radius":
+        spec.radius[1] = -1e-3
+    elif case == "nan_position":
+        spec.pos[0, 2] = float("nan")
+    elif case == "short_period":
+        spec.box = (0.005, 0.1, 0.0)  # must exceed 2 (r_i + r_j)
+    elif case == "cadence_without_skin":
+        kw = dict(rebuild_every=4, skin=0.0)
+    elif case == "band_ratio":
+        kw = dict(band_ratio=1.0)
+    elif case == "block":
+        kw = dict(block=100)
+    with pytest.raises(LprError) as e:
+        Bed(spec, **kw)
+    assert e.value.status == -1
+
+
+def test_more_partners_than_slots_latches_capacity():
+    """A 1 mm sphere overlapped by 20 spheres of 2 mm owns all 20 pairs (the
+    smaller radius owns), more than its 16 slots: the step reports the
+    capacity fault and the bed stays latched."""
+    from paper_2501_05300_amd.lprdem import Bed, CapacityError, LprError
+    c = np.array([0.05, 0.05, 0.05])
+    golden = math.pi * (3.0 - math.sqrt(5.0))
+    pts = []
+    for q in range(20):  # Fibonacci points on a sphere of radius 2.9 mm
+        z = 1.0 - 2.0 * (q + 0.5) / 20
+        rr = math.sqrt(1.0 - z * z)
+        pts.append(c + 2.9e-3 * np.array([rr * math.cos(golden * q), rr * math.sin(golden * q), z]))
+    spec = spec_of([c] + pts, [1e-3] + [2e-3] * 20, params=beds.paper_params(E=1e6))
+    bed = Bed(spec)
+    bed.step(1)
+    with pytest.raises(CapacityError):
+        bed.sync()
+    with pytest.raises(LprError):
+        bed.step(1)
+        bed.sync()
+    x, _, _ = bed.state()  # the state stays readable
+    assert np.all(np.isfinite(x))
+
+
+def test_coincident_spheres_match_oracle():
+    """d = 0: the pair's normal is +z (the reading for a degenerate
+    direction); the force on the pair and a third, ordinary contact match
+    the oracle."""
+    from paper_2501_05300_amd.lprdem import Bed
+    spec = spec_of([[0.05, 0.05, 0.05], [0.05, 0.05, 0.05], [0.0535, 0.05, 0.05]], [2e-3, 2e-3, 1.5e-3],
+                   params=beds.paper_params(E=1e6))
+    bed = Bed(spec, record_forces=True)
+    res = compare_one_step(spec, bed)
+    print(res)
+    assert res["contacts_equal"] and res["n_contacts"] == 3
+    assert res["force_rel"] < 1e-5 and res["torque_rel"] < 1e-5
+    F, _ = bed.forces()
+    # stable id 0 owns the coincident pair (equal radii, smaller id) and is
+    # pushed along -n = -z, its partner along +z
+    assert F[0, 2] < 0 < F[1, 2]
