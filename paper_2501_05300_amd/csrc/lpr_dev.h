@@ -67,6 +67,7 @@ struct LevelGrid {
   int32_t n[3];      // cells per axis
   int32_t per[3];    // axis wraps
   int64_t base;      // first global cell id
+  double rmax;       // largest radius binned at this level
 };
 
 // Per-bed constants.

@@ -53,26 +53,6 @@ LPR_DEV_INLINE int cell_axis(const LevelGrid& G, int a, double x) {
   return c;
 }
 
-// Neighbour cells along one axis (de-duplicated on short periodic axes).
-LPR_DEV_INLINE int axis_neighbours(const LevelGrid& G, int a, int c, int out[3]) {
-  const int n = G.n[a];
-  if (G.per[a]) {
-    if (n <= 3) {
-      for (int q = 0; q < n; ++q) out[q] = q;
-      return n;
-    }
-    out[0] = (c == 0) ? n - 1 : c - 1;
-    out[1] = c;
-    out[2] = (c == n - 1) ? 0 : c + 1;
-    return 3;
-  }
-  int m = 0;
-  if (c - 1 >= 0) out[m++] = c - 1;
-  out[m++] = c;
-  if (c + 1 < n) out[m++] = c + 1;
-  return m;
-}
-
 // Work block handled by launch block b of a grid of g blocks: the blocks
 // that the hardware places on one XCD (b mod 8) take one contiguous range of
 // particles, so neighbours they gather share that XCD's L2.
@@ -241,13 +221,16 @@ void launch_scan(uint32_t* cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipSt
 // ---------------------------------------------------------------------------
 // owner-side search with history carry-over
 //
-// Each thread walks the one-cell neighbourhood of its particle at its own
-// level and every coarser one (a coarser level only when its occupied rows
-// reach the particle's row).  The neighbourhood is at most 3 x 3 rows of up
-// to 3 cells; the cells of a row are consecutive in the cell order, so the
-// row is one range of the cell lists (two where the x axis wraps).  All 18
-// range bounds are loaded before the first candidate.  A first pass reads
-// the 16-byte FP32 copy of each candidate, eight per round, and keeps the
+// Each thread walks the neighbourhood of its particle at its own level and
+// every coarser one (a coarser level only when its occupied rows reach the
+// particle's row): along each axis the particle's cell and those of its two
+// neighbours that lie within r_i + r_max(level) + skin of it.  That is at
+// most 3 x 3 rows of up to 3 cells; the cells of a row are consecutive in
+// the cell order, so the row is one range of the cell lists (two where the x
+// axis wraps).  All 18 range bounds are loaded before the first candidate.
+// A first pass reads the 16-byte FP32 copy of each candidate, eight per
+// round (a round that passes the end of a row continues into the next), and
+// keeps the
 // ones within a conservative FP32 distance bound (and not owned by the
 // partner); a second pass reads the kept candidates' FP64 records, four at a
 // time, and applies the owner rule and the exact predicate.  Accepted
@@ -255,47 +238,80 @@ void launch_scan(uint32_t* cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipSt
 // from the previous lists.
 
 constexpr int SBS = 64;   // threads per search block
-constexpr int PCAP = 24;  // first-pass candidates kept per particle
+constexpr int PCAP = 22;  // first-pass candidates kept per particle
+constexpr int RT = 18;    // rows of one level (the row table's length)
+static_assert(RT >= K, "the row table's space also holds the slot sort");
 
-// Cell ranges [xa, xb) along x covering cx - 1 .. cx + 1 (two pieces where a
-// periodic axis wraps; the whole axis when it has three cells or fewer).
-LPR_DEV_INLINE int x_pieces(const LevelGrid& G, int cx, int xa[2], int xb[2]) {
-  const int n = G.n[0];
-  if (!G.per[0]) {
-    xa[0] = max(0, cx - 1);
-    xb[0] = min(n, cx + 2);
-    return 1;
+// Cells along axis a that can hold a partner closer than `reach` to the
+// coordinate x: the range [c + lo, c + hi] around the particle's cell c, with
+// lo, hi in {-1, 0, 1} (a cell is at least `reach` wide, so one neighbour on
+// either side is the most that is ever needed).  The bounds come from the
+// cell coordinate of x -+ reach with a slack of 1e-9 cell, far above the
+// rounding of the cell coordinates, so no cell that holds such a partner is
+// dropped.
+LPR_DEV_INLINE void axis_span(const LevelGrid& G, int a, double x, double reach, int& c, int& lo, int& hi) {
+#pragma clang fp contract(off)
+  const int n = G.n[a];
+  c = cell_axis(G, a, x);
+  const double dr = reach * G.inv_w[a] + 1e-9;
+  if (G.per[a]) {
+    // offsets from the cell coordinate as cell_axis clamps it, so they are
+    // relative to c
+    const double f = fmin(fmax((x - G.lo[a]) * G.inv_w[a], -1.0), (double)n);
+    const double fc = floor(f);
+    lo = (floor(f - dr) < fc) ? -1 : 0;
+    hi = (floor(f + dr) > fc) ? 1 : 0;
+    return;
   }
-  if (n <= 3) {
-    xa[0] = 0;
-    xb[0] = n;
-    return 1;
-  }
-  if (cx == 0) {
-    xa[0] = 0; xb[0] = 2;
-    xa[1] = n - 1; xb[1] = n;
-    return 2;
-  }
-  if (cx == n - 1) {
-    xa[0] = n - 2; xb[0] = n;
-    xa[1] = 0; xb[1] = 1;
-    return 2;
-  }
-  xa[0] = cx - 1;
-  xb[0] = cx + 2;
-  return 1;
+  // binning clamps a cell index to the grid, so the span's ends are clamped
+  // the same way (particles beyond an edge sit in the edge cell)
+  const double f = fmin(fmax((x - G.lo[a]) * G.inv_w[a], -1073741824.0), 1073741824.0);
+  const int a0 = min(max((int)floor(f - dr), 0), n - 1), b0 = min(max((int)floor(f + dr), 0), n - 1);
+  lo = max(a0, c - 1) - c;
+  hi = min(b0, c + 1) - c;
 }
 
-// Cell-list bounds of the particle's neighbour rows at one level.
-LPR_DEV_INLINE void row_bounds(const DevBufs& d, const LevelGrid& G, const double4& pi, uint32_t q0[18],
+// Cell-list bounds of the particle's neighbour rows at one level (rows along
+// x of the needed (y, z) cells; the cells of a row are consecutive in the
+// cell order): the nine first pieces, then the nine second pieces, which are
+// empty unless the x range wraps.  Short periodic axes (three cells or
+// fewer) take every cell once.
+LPR_DEV_INLINE void row_bounds(const DevBufs& d, const LevelGrid& G, const double4& pi, double reach, uint32_t q0[18],
                                uint32_t q1[18]) {
+  int cx, xl, xh, cy, yl, yh, cz, zl, zh;
+  axis_span(G, 0, pi.x, reach, cx, xl, xh);
+  axis_span(G, 1, pi.y, reach, cy, yl, yh);
+  axis_span(G, 2, pi.z, reach, cz, zl, zh);
   int ly[3], lz[3], xa[2], xb[2];
-  const int nyl = axis_neighbours(G, 1, cell_axis(G, 1, pi.y), ly);
-  const int nzl = axis_neighbours(G, 2, cell_axis(G, 2, pi.z), lz);
-  const int nxp = x_pieces(G, cell_axis(G, 0, pi.x), xa, xb);
+  int nyl = 0, nzl = 0, nxp = 0;
+  if (G.per[1] && G.n[1] <= 3) {
+    for (int q = 0; q < G.n[1]; ++q) ly[nyl++] = q;
+  } else {
+    for (int o = yl; o <= yh; ++o) {
+      int y = cy + o;
+      if (G.per[1]) y = (y < 0) ? y + G.n[1] : (y >= G.n[1] ? y - G.n[1] : y);
+      ly[nyl++] = y;
+    }
+  }
+  for (int o = zl; o <= zh; ++o) lz[nzl++] = cz + o;  // z never wraps
+  {
+    const int n = G.n[0];
+    if (G.per[0] && n <= 3) {
+      xa[0] = 0; xb[0] = n; nxp = 1;
+    } else if (xh >= xl) {
+      const int a0 = cx + xl, b0 = cx + xh + 1;  // [a0, b0), may leave [0, n) on a periodic axis
+      if (a0 < 0) {
+        xa[0] = 0; xb[0] = b0; xa[1] = a0 + n; xb[1] = n; nxp = 2;
+      } else if (b0 > n) {
+        xa[0] = a0; xb[0] = n; xa[1] = 0; xb[1] = b0 - n; nxp = 2;
+      } else {
+        xa[0] = a0; xb[0] = b0; nxp = 1;
+      }
+    }
+  }
 #pragma unroll
   for (int r = 0; r < 18; ++r) {
-    const int a = r / 6, b = (r / 2) % 3, p = r & 1;
+    const int p = r / 9, a = (r % 9) / 3, b = r % 3;
     q0[r] = 0u;
     q1[r] = 0u;
     if (a < nzl && b < nyl && p < nxp) {
@@ -319,8 +335,12 @@ LPR_DEV_INLINE bool owner_candidate(const BedConst& bc, const double4& pi, int32
 }
 
 __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho) {
-  __shared__ int32_t c_sid[K][SBS];
+  // per lane: the non-empty rows of the level being walked, packed as
+  // (first cell-list position << 6 | length); once the walk is done the same
+  // space holds the accepted partners' stable ids for the slot sort
+  __shared__ uint32_t rtab[RT][SBS];
   __shared__ int32_t c_idx[PCAP][SBS];  // kept candidates, then the accepted ones
+  int32_t (*const c_sid)[SBS] = reinterpret_cast<int32_t (*)[SBS]>(rtab);
   const int t = threadIdx.x;
   // each XCD takes one contiguous range of particles, so the neighbour rows
   // its blocks read overlap in that XCD's L2
@@ -343,6 +363,12 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
   const BedConst bc = d.beds[m >> 8];
   const int lev_i = (int)(m & 0xffu);
   const double4 pi = d.st[s][i].x;
+  // the previous lists, read now so that their latency hides behind the walk
+  const uint32_t fo = d.cflag[ho][i];
+  const int cnt_old = d.own_cnt[lo][i];
+  int32_t old_j[K];
+#pragma unroll
+  for (int k2 = 0; k2 < K; ++k2) old_j[k2] = (k2 < cnt_old) ? d.own_idx[lo][k2 * N + i] : -1;
   const float rif = (float)pi.w;
   const int32_t si = d.sid[i];
   const double skin = (double)bc.skin;
@@ -356,7 +382,7 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
   const float mag = fmaxf(fmaxf(fabsf(pfx), fabsf(pfy)), fmaxf(fabsf(pfz), fmaxf(Lx, Ly)));
   const float reach = rif + bc.skin + mag * 0x1p-19f;
   int np = 0;
-  for (int lev = lev_i; lev < bc.nlev; ++lev) {
+  for (int lev = lev_i; lev < bc.nlev && np <= PCAP; ++lev) {
     const int gl = bc.lev0 + lev;
     const LevelGrid G = d.levels[gl];
     if (lev > lev_i) {
@@ -365,26 +391,65 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
       const int zu = row_unclamped(G, pi.z);
       if (zu < d.zext[2 * gl] - 1 || zu > d.zext[2 * gl + 1] + 1) continue;
     }
-    uint32_t q0[18], q1[18];
-    row_bounds(d, G, pi, q0, q1);
+    int nr = 0;
+    bool wide = false;
+    {
+      uint32_t q0[18], q1[18];
+      row_bounds(d, G, pi, pi.w + G.rmax + skin, q0, q1);
 #pragma unroll
-    for (int r = 0; r < 18; ++r) {
-      for (uint32_t q = q0[r]; q < q1[r]; q += 8) {
-        float4 c[8];
+      for (int r = 0; r < 18; ++r) {
+        const uint32_t len = q1[r] - q0[r];
+        if (len > 0u) {
+          wide = wide || len > 63u || q0[r] >= (1u << 26);
+          rtab[nr][t] = (q0[r] << 6) | (len & 63u);
+          ++nr;
+        }
+      }
+    }
+    if (wide) {  // a row too long (or a list too large) for the packed table
+      np = PCAP + 1;
+      break;
+    }
+    // the rows are walked as one stream, eight positions per round, so a
+    // lane's rounds follow its own candidate count; at the top of a round
+    // position q lies in row ri
+    int ri = 0;
+    uint32_t q = 0u, e = 0u;
+    if (nr > 0) {
+      const uint32_t w = rtab[0][t];
+      q = w >> 6;
+      e = q + (w & 63u);
+    }
+    while (ri < nr) {
+      float4 c[8];
+      uint32_t qa[8];
+      bool ok[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) c[u] = d.cpf[(q + u < q1[r]) ? q + u : q];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (q + u >= q1[r] || c[u].w < rif) continue;  // j owns pairs with a smaller radius
-          float fx = c[u].x - pfx, fy = c[u].y - pfy;
-          const float fz = c[u].z - pfz;
-          if (perx) fx = (fx > 0.5f * Lx) ? fx - Lx : ((fx < -0.5f * Lx) ? fx + Lx : fx);
-          if (pery) fy = (fy > 0.5f * Ly) ? fy - Ly : ((fy < -0.5f * Ly) ? fy + Ly : fy);
-          const float Rf = reach + c[u].w;
-          if (fx * fx + fy * fy + fz * fz < Rf * Rf) {
-            if (np < PCAP) c_idx[np][t] = (int32_t)(q + u);
-            ++np;
+      for (int u = 0; u < 8; ++u) {
+        ok[u] = ri < nr;
+        qa[u] = q;
+        if (ok[u] && ++q >= e) {
+          ++ri;
+          if (ri < nr) {
+            const uint32_t w = rtab[ri][t];
+            q = w >> 6;
+            e = q + (w & 63u);
           }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) c[u] = d.cpf[ok[u] ? qa[u] : qa[0]];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (!ok[u] || c[u].w < rif) continue;  // j owns pairs with a smaller radius
+        float fx = c[u].x - pfx, fy = c[u].y - pfy;
+        const float fz = c[u].z - pfz;
+        if (perx) fx = (fx > 0.5f * Lx) ? fx - Lx : ((fx < -0.5f * Lx) ? fx + Lx : fx);
+        if (pery) fy = (fy > 0.5f * Ly) ? fy - Ly : ((fy < -0.5f * Ly) ? fy + Ly : fy);
+        const float Rf = reach + c[u].w;
+        if (fx * fx + fy * fy + fz * fz < Rf * Rf) {
+          if (np < PCAP) c_idx[np][t] = (int32_t)qa[u];
+          ++np;
         }
       }
     }
@@ -401,7 +466,7 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
         if (zu < d.zext[2 * gl] - 1 || zu > d.zext[2 * gl + 1] + 1) continue;
       }
       uint32_t q0[18], q1[18];
-      row_bounds(d, G, pi, q0, q1);
+      row_bounds(d, G, pi, pi.w + G.rmax + skin, q0, q1);
       for (int r = 0; r < 18; ++r)
         for (uint32_t q = q0[r]; q < q1[r]; ++q)
           if (owner_candidate(bc, pi, si, skin, d.crec[q])) {
@@ -437,8 +502,6 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
     atomicOr(d.err, ERR_CAPACITY);
     cnt = K;
   }
-  // cell-list positions -> storage indices
-  for (int a = 0; a < cnt; ++a) c_idx[a][t] = d.cell_list[c_idx[a][t]];
   // canonical slot order: ascending partner stable id
   for (int a = 1; a < cnt; ++a) {
     const int32_t ks = c_sid[a][t], kj = c_idx[a][t];
@@ -451,28 +514,45 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
     c_sid[b + 1][t] = ks;
     c_idx[b + 1][t] = kj;
   }
-  const uint32_t fo = d.cflag[ho][i];
+  // slots four at a time, with every read and atomic of a group in flight
+  // together: storage index of the partner, its reverse-list rank, the slot
+  // it held in the previous lists and that slot's spring history (a slot
+  // whose pair was not in contact holds zero history, so readers need not
+  // consult the contact flags)
   uint32_t fn = fo & 0xffff0000u;
-  const int cnt_old = d.own_cnt[lo][i];
-  for (int k = 0; k < cnt; ++k) {
-    const int32_t j = c_idx[k][t];
-    d.own_idx[ln][k * N + i] = j;
-    d.own_rank[k * N + i] = atomicAdd(&d.rev_cnt[j], 1u);
-    // a slot whose pair was not in contact holds zero history, so readers
-    // need not consult the contact flags
-    HRec hr;
-    hr.t = make_float4(0.f, 0.f, 0.f, 0.f);
-    hr.r = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int k2 = 0; k2 < cnt_old; ++k2) {
-      if (d.own_idx[lo][k2 * N + i] == j) {
-        if ((fo >> k2) & 1u) {
-          hr = d.hist[ho][k2 * N + i];
-          fn |= 1u << k;
-        }
-        break;
+  for (int k0 = 0; k0 < cnt; k0 += 4) {
+    int32_t jj[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) jj[u] = (k0 + u < cnt) ? d.cell_list[c_idx[k0 + u][t]] : -2;
+    uint32_t rk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) rk[u] = (k0 + u < cnt) ? atomicAdd(&d.rev_cnt[jj[u]], 1u) : 0u;
+    int mk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      mk[u] = -1;
+#pragma unroll
+      for (int k2 = K - 1; k2 >= 0; --k2)
+        if (old_j[k2] == jj[u]) mk[u] = k2;
+    }
+    HRec hr[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      hr[u].t = make_float4(0.f, 0.f, 0.f, 0.f);
+      hr[u].r = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (mk[u] >= 0 && ((fo >> mk[u]) & 1u)) {
+        hr[u] = d.hist[ho][(int64_t)mk[u] * N + i];
+        fn |= 1u << (k0 + u);
       }
     }
-    d.hist[hn][k * N + i] = hr;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + u < cnt) {
+        const int64_t o = (int64_t)(k0 + u) * N + i;
+        d.own_idx[ln][o] = jj[u];
+        d.own_rank[o] = rk[u];
+        d.hist[hn][o] = hr[u];
+      }
   }
   for (int w = 0; w < bc.nwall; ++w)
     if ((fo >> (WALL_BIT + w)) & 1u) {

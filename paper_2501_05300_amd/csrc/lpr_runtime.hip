@@ -277,6 +277,7 @@ void plan_bed(const lpr_bed_desc* D, double band_ratio, double cell_factor, doub
       H.skin_cap = std::min(H.skin_cap, w - 2.0 * rm);
     }
     G.base = cell_base;
+    G.rmax = rm;
     cell_base += (int64_t)G.n[0] * G.n[1] * G.n[2];
     levels.push_back(G);
   }
