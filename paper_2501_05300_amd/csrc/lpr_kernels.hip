@@ -275,8 +275,10 @@ LPR_DEV_INLINE void axis_span(const LevelGrid& G, int a, double x, double reach,
 // x of the needed (y, z) cells; the cells of a row are consecutive in the
 // cell order): the nine first pieces, then the nine second pieces, which are
 // empty unless the x range wraps.  Short periodic axes (three cells or
-// fewer) take every cell once.
-LPR_DEV_INLINE void row_bounds(const DevBufs& d, const LevelGrid& G, const double4& pi, double reach, uint32_t q0[18],
+// fewer) take every cell once.  Returns whether a cell lies across a
+// periodic edge from the particle (only then can a separation need the
+// minimum image).
+LPR_DEV_INLINE bool row_bounds(const DevBufs& d, const LevelGrid& G, const double4& pi, double reach, uint32_t q0[18],
                                uint32_t q1[18]) {
   int cx, xl, xh, cy, yl, yh, cz, zl, zh;
   axis_span(G, 0, pi.x, reach, cx, xl, xh);
@@ -293,11 +295,13 @@ LPR_DEV_INLINE void row_bounds(const DevBufs& d, const LevelGrid& G, const doubl
       ly[nyl++] = y;
     }
   }
+  bool across = G.per[1] && (G.n[1] <= 3 || cy + yl < 0 || cy + yh >= G.n[1]);
   for (int o = zl; o <= zh; ++o) lz[nzl++] = cz + o;  // z never wraps
   {
     const int n = G.n[0];
     if (G.per[0] && n <= 3) {
       xa[0] = 0; xb[0] = n; nxp = 1;
+      across = true;
     } else if (xh >= xl) {
       const int a0 = cx + xl, b0 = cx + xh + 1;  // [a0, b0), may leave [0, n) on a periodic axis
       if (a0 < 0) {
@@ -318,6 +322,63 @@ LPR_DEV_INLINE void row_bounds(const DevBufs& d, const LevelGrid& G, const doubl
       const int64_t rb = G.base + ((int64_t)lz[a] * G.n[1] + ly[b]) * G.n[0];
       q0[r] = d.cell_start[rb + xa[p]];
       q1[r] = d.cell_start[rb + xb[p]];
+    }
+  }
+  return across || nxp == 2;
+}
+
+// First pass over one level's rows (the row table holds nr packed rows):
+// each lane walks its rows as one stream, eight positions per round, so its
+// rounds follow its own candidate count, and keeps the candidates that pass
+// a conservative FP32 distance bound and are not owned by the partner (a
+// larger radius owns nothing here).  WRAP takes the minimum image on the
+// periodic axes; a wave whose lanes have no cell across a periodic edge
+// skips it, since then every separation is already the nearest image.
+template <bool WRAP>
+LPR_DEV_INLINE void walk_rows(const float4* __restrict__ cpf, const uint32_t (*rtab)[SBS], int32_t (*c_idx)[SBS], int t,
+                              int nr, float pfx, float pfy, float pfz, float rif, float reach, bool perx, bool pery,
+                              float Lx, float Ly, int& np) {
+  // at the top of a round position q lies in row ri
+  int ri = 0;
+  uint32_t q = 0u, e = 0u;
+  if (nr > 0) {
+    const uint32_t w = rtab[0][t];
+    q = w >> 6;
+    e = q + (w & 63u);
+  }
+  while (ri < nr) {
+    float4 c[8];
+    uint32_t qa[8];
+    bool ok[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      ok[u] = ri < nr;
+      qa[u] = q;
+      if (ok[u] && ++q >= e) {
+        ++ri;
+        if (ri < nr) {
+          const uint32_t w = rtab[ri][t];
+          q = w >> 6;
+          e = q + (w & 63u);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = cpf[ok[u] ? qa[u] : qa[0]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (!ok[u] || c[u].w < rif) continue;  // j owns pairs with a smaller radius
+      float fx = c[u].x - pfx, fy = c[u].y - pfy;
+      const float fz = c[u].z - pfz;
+      if (WRAP) {
+        if (perx) fx = (fx > 0.5f * Lx) ? fx - Lx : ((fx < -0.5f * Lx) ? fx + Lx : fx);
+        if (pery) fy = (fy > 0.5f * Ly) ? fy - Ly : ((fy < -0.5f * Ly) ? fy + Ly : fy);
+      }
+      const float Rf = reach + c[u].w;
+      if (fx * fx + fy * fy + fz * fz < Rf * Rf) {
+        if (np < PCAP) c_idx[np][t] = (int32_t)qa[u];
+        ++np;
+      }
     }
   }
 }
@@ -392,10 +453,10 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
       if (zu < d.zext[2 * gl] - 1 || zu > d.zext[2 * gl + 1] + 1) continue;
     }
     int nr = 0;
-    bool wide = false;
+    bool wide = false, across;
     {
       uint32_t q0[18], q1[18];
-      row_bounds(d, G, pi, pi.w + G.rmax + skin, q0, q1);
+      across = row_bounds(d, G, pi, pi.w + G.rmax + skin, q0, q1);
 #pragma unroll
       for (int r = 0; r < 18; ++r) {
         const uint32_t len = q1[r] - q0[r];
@@ -410,49 +471,10 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
       np = PCAP + 1;
       break;
     }
-    // the rows are walked as one stream, eight positions per round, so a
-    // lane's rounds follow its own candidate count; at the top of a round
-    // position q lies in row ri
-    int ri = 0;
-    uint32_t q = 0u, e = 0u;
-    if (nr > 0) {
-      const uint32_t w = rtab[0][t];
-      q = w >> 6;
-      e = q + (w & 63u);
-    }
-    while (ri < nr) {
-      float4 c[8];
-      uint32_t qa[8];
-      bool ok[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        ok[u] = ri < nr;
-        qa[u] = q;
-        if (ok[u] && ++q >= e) {
-          ++ri;
-          if (ri < nr) {
-            const uint32_t w = rtab[ri][t];
-            q = w >> 6;
-            e = q + (w & 63u);
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) c[u] = d.cpf[ok[u] ? qa[u] : qa[0]];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (!ok[u] || c[u].w < rif) continue;  // j owns pairs with a smaller radius
-        float fx = c[u].x - pfx, fy = c[u].y - pfy;
-        const float fz = c[u].z - pfz;
-        if (perx) fx = (fx > 0.5f * Lx) ? fx - Lx : ((fx < -0.5f * Lx) ? fx + Lx : fx);
-        if (pery) fy = (fy > 0.5f * Ly) ? fy - Ly : ((fy < -0.5f * Ly) ? fy + Ly : fy);
-        const float Rf = reach + c[u].w;
-        if (fx * fx + fy * fy + fz * fz < Rf * Rf) {
-          if (np < PCAP) c_idx[np][t] = (int32_t)qa[u];
-          ++np;
-        }
-      }
-    }
+    if (__any(across))
+      walk_rows<true>(d.cpf, rtab, c_idx, t, nr, pfx, pfy, pfz, rif, reach, perx, pery, Lx, Ly, np);
+    else
+      walk_rows<false>(d.cpf, rtab, c_idx, t, nr, pfx, pfy, pfz, rif, reach, perx, pery, Lx, Ly, np);
   }
   if (np > PCAP) {
     // more kept candidates than the list holds: exact walk from the FP64
