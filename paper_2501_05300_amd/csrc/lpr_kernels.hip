@@ -76,7 +76,8 @@ LPR_DEV_INLINE int row_unclamped(const LevelGrid& G, double z) {
 // Bins every particle into the grid of its own level and widens the level's
 // occupied z-row range (monotone, so a stale range is still a superset).
 // Consecutive particles mostly share cells: the lanes of a wave that fall in
-// one cell take their ranks from a single atomic (ballot, prefix count).
+// one cell take their ranks from a single atomic (ballot, prefix count), and
+// the wave's atomics for all its cells go out in one instruction.
 __global__ void k_bin(DevBufs d, int s) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= d.N || latched(d.err)) return;
@@ -89,20 +90,26 @@ __global__ void k_bin(DevBufs d, int s) {
   const int cx = cell_axis(G, 0, p.x), cy = cell_axis(G, 1, p.y), cz = cell_axis(G, 2, p.z);
   const int32_t c = (int32_t)(G.base + ((int64_t)cz * G.n[1] + cy) * G.n[0] + cx);
   d.pcell[i] = c;
+  // group the wave's lanes by cell (votes only), then one atomic per group,
+  // all groups' atomics issued together
   const int lane = (int)(threadIdx.x & 63u);
   uint64_t todo = __ballot(1);  // the wave's active lanes
-  uint32_t rank = 0u;
+  int leader_of = lane;
+  uint32_t off = 0u, gsize = 0u;
   while (todo != 0ull) {
     const int leader = __ffsll((unsigned long long)todo) - 1;
     const int32_t key = __shfl(c, leader, 64);
     const uint64_t grp = __ballot(c == key) & todo;
-    uint32_t base = 0u;
-    if (lane == leader) base = atomicAdd(&d.cell_cnt[key], (uint32_t)__popcll(grp));
-    base = __shfl(base, leader, 64);
-    if ((grp >> lane) & 1ull) rank = base + (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
+    if ((grp >> lane) & 1ull) {
+      leader_of = leader;
+      off = (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
+    }
+    if (lane == leader) gsize = (uint32_t)__popcll(grp);
     todo &= ~grp;
   }
-  d.prank[i] = rank;
+  uint32_t base = 0u;
+  if (lane == leader_of) base = atomicAdd(&d.cell_cnt[c], gsize);
+  d.prank[i] = __shfl(base, leader_of, 64) + off;
   const int zu = row_unclamped(G, p.z);
   if (zu < *(const volatile int*)&d.zext[2 * gl]) atomicMin(&d.zext[2 * gl], zu);
   if (zu > *(const volatile int*)&d.zext[2 * gl + 1]) atomicMax(&d.zext[2 * gl + 1], zu);
@@ -597,9 +604,21 @@ __global__ void k_rev_scatter(DevBufs d, int l) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= d.N || latched(d.err)) return;
   const int cnt = d.own_cnt[l][i];
-  for (int k = 0; k < cnt; ++k) {
-    const int32_t j = d.own_idx[l][k * d.N + i];
-    d.rev_ent[d.rev_start[j] + d.own_rank[k * d.N + i]] = ((uint32_t)i << 4) | (uint32_t)k;
+  // slots four at a time, their reads in flight together
+  for (int k0 = 0; k0 < cnt; k0 += 4) {
+    int32_t j[4];
+    uint32_t rk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      j[u] = (k0 + u < cnt) ? d.own_idx[l][(int64_t)(k0 + u) * d.N + i] : 0;
+      rk[u] = (k0 + u < cnt) ? d.own_rank[(int64_t)(k0 + u) * d.N + i] : 0u;
+    }
+    uint32_t at[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) at[u] = (k0 + u < cnt) ? d.rev_start[j[u]] + rk[u] : 0u;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + u < cnt) d.rev_ent[at[u]] = ((uint32_t)i << 4) | (uint32_t)(k0 + u);
   }
 }
 
@@ -615,6 +634,33 @@ __global__ void k_rev_sort(DevBufs d) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= d.N || latched(d.err)) return;
   const uint32_t a = d.rev_start[j], b = d.rev_start[j + 1];
+  if (b - a <= 8u) {
+    // short lists (nearly all): entries and owner ids read together, sorted
+    // in registers by an odd-even transposition network, written once
+    constexpr int32_t KMAX = 0x7fffffff;
+    uint32_t e[8];
+    int32_t key[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) e[u] = (a + u < b) ? d.rev_ent[a + u] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) key[u] = (a + u < b) ? d.sid[e[u] >> 4] : KMAX;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int u = r & 1; u + 1 < 8; u += 2)
+        if (key[u + 1] < key[u]) {
+          const int32_t tk = key[u];
+          key[u] = key[u + 1];
+          key[u + 1] = tk;
+          const uint32_t te = e[u];
+          e[u] = e[u + 1];
+          e[u + 1] = te;
+        }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (a + u < b) d.rev_ent[a + u] = e[u];
+    return;
+  }
   for (uint32_t q = a + 1; q < b; ++q) {
     const uint32_t e = d.rev_ent[q];
     const int32_t key = d.sid[e >> 4];
