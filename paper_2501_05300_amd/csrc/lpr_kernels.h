@@ -45,7 +45,8 @@ struct DevBufs {
   uint32_t* scan_tmp;
   CRec* crec;            // position, radius and stable id in cell-list order (rebuild)
   float4* cpf;           // FP32 (x, y, z, r) in cell-list order (rebuild)
-  int32_t* zext;         // [levels][2] occupied z-row range (monotone)
+  uint32_t* zext;        // [levels][2] highest z and highest -z of the level's centres seen
+                         // (order-preserving FP32 bits, 0 = none; monotone)
   float* disp;           // distance bound moved since the last rebuild
   uint32_t* viol;        // [2] skin-exceeded flags, by state parity
   // tables

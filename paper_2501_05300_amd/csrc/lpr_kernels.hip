@@ -66,15 +66,20 @@ LPR_DEV_INLINE int64_t xcd_block(int64_t b, int64_t g) {
 // ---------------------------------------------------------------------------
 // binning
 
-// Cell row of z in a level grid before clamping (bounded to +-2^30).
-LPR_DEV_INLINE int row_unclamped(const LevelGrid& G, double z) {
-#pragma clang fp contract(off)
-  const double f = fmin(fmax((z - G.lo[2]) * G.inv_w[2], -1073741824.0), 1073741824.0);
-  return (int)floor(f);
+// FP32 value <-> unsigned key with the same order (0 lies below every
+// finite value), for extents kept with integer atomicMax.
+LPR_DEV_INLINE uint32_t ord_key(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+LPR_DEV_INLINE float ord_val(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
 // Bins every particle into the grid of its own level and widens the level's
-// occupied z-row range (monotone, so a stale range is still a superset).
+// recorded range of centre heights (monotone, so a stale range is still a
+// superset; one atomic per wave and bound, and only when the wave's value
+// extends it).
 // Consecutive particles mostly share cells: the lanes of a wave that fall in
 // one cell take their ranks from a single atomic (ballot, prefix count), and
 // the wave's atomics for all its cells go out in one instruction.
@@ -110,9 +115,17 @@ __global__ void k_bin(DevBufs d, int s) {
   uint32_t base = 0u;
   if (lane == leader_of) base = atomicAdd(&d.cell_cnt[c], gsize);
   d.prank[i] = __shfl(base, leader_of, 64) + off;
-  const int zu = row_unclamped(G, p.z);
-  if (zu < *(const volatile int*)&d.zext[2 * gl]) atomicMin(&d.zext[2 * gl], zu);
-  if (zu > *(const volatile int*)&d.zext[2 * gl + 1]) atomicMax(&d.zext[2 * gl + 1], zu);
+  uint32_t khi = ord_key((float)p.z), klo = ord_key(-(float)p.z);
+  // a full wave whose lanes share one level (nearly every wave) reduces first
+  const int gl0 = __shfl(gl, __ffsll((unsigned long long)__ballot(1)) - 1, 64);
+  if (__ballot(1) == ~0ull && __all(gl == gl0)) {
+    for (int o = 32; o >= 1; o >>= 1) {
+      khi = max(khi, (uint32_t)__shfl_xor((int)khi, o, 64));
+      klo = max(klo, (uint32_t)__shfl_xor((int)klo, o, 64));
+    }
+  }
+  if (khi > *(const volatile uint32_t*)&d.zext[2 * gl]) atomicMax(&d.zext[2 * gl], khi);
+  if (klo > *(const volatile uint32_t*)&d.zext[2 * gl + 1]) atomicMax(&d.zext[2 * gl + 1], klo);
 }
 
 void launch_bin(const DevBufs& d, int s, hipStream_t st) {
@@ -278,60 +291,72 @@ LPR_DEV_INLINE void axis_span(const LevelGrid& G, int a, double x, double reach,
   hi = min(b0, c + 1) - c;
 }
 
-// Cell-list bounds of the particle's neighbour rows at one level (rows along
-// x of the needed (y, z) cells; the cells of a row are consecutive in the
-// cell order): the nine first pieces, then the nine second pieces, which are
-// empty unless the x range wraps.  Short periodic axes (three cells or
-// fewer) take every cell once.  Returns whether a cell lies across a
-// periodic edge from the particle (only then can a separation need the
-// minimum image).
-LPR_DEV_INLINE bool row_bounds(const DevBufs& d, const LevelGrid& G, const double4& pi, double reach, uint32_t q0[18],
-                               uint32_t q1[18]) {
+// The particle's neighbour rows at one level: rows along x of the needed
+// (y, z) cells (the cells of a row are consecutive in the cell order), each
+// in one piece, or two where the x range wraps.  Short periodic axes (three
+// cells or fewer) take every cell once.
+struct RowSet {
+  int y0, nyl;          // rows y0 .. y0 + nyl - 1 (wrapped on a periodic axis)
+  int z0, nzl;          // rows z0 .. z0 + nzl - 1
+  int xa0, xb0, xa1, xb1, nxp;  // x pieces [xa, xb)
+  bool across;  // a cell lies across a periodic edge from the particle (only
+                // then can a separation need the minimum image)
+};
+
+LPR_DEV_INLINE void row_set(const LevelGrid& G, const double4& pi, double reach, RowSet& R) {
   int cx, xl, xh, cy, yl, yh, cz, zl, zh;
   axis_span(G, 0, pi.x, reach, cx, xl, xh);
   axis_span(G, 1, pi.y, reach, cy, yl, yh);
   axis_span(G, 2, pi.z, reach, cz, zl, zh);
-  int ly[3], lz[3], xa[2], xb[2];
-  int nyl = 0, nzl = 0, nxp = 0;
   if (G.per[1] && G.n[1] <= 3) {
-    for (int q = 0; q < G.n[1]; ++q) ly[nyl++] = q;
+    R.y0 = 0;
+    R.nyl = G.n[1];
   } else {
-    for (int o = yl; o <= yh; ++o) {
-      int y = cy + o;
-      if (G.per[1]) y = (y < 0) ? y + G.n[1] : (y >= G.n[1] ? y - G.n[1] : y);
-      ly[nyl++] = y;
+    R.y0 = cy + yl;
+    R.nyl = max(0, yh - yl + 1);
+  }
+  R.across = G.per[1] && (G.n[1] <= 3 || cy + yl < 0 || cy + yh >= G.n[1]);
+  R.z0 = cz + zl;  // z never wraps
+  R.nzl = max(0, zh - zl + 1);
+  const int n = G.n[0];
+  R.xa0 = R.xb0 = R.xa1 = R.xb1 = 0;
+  R.nxp = 0;
+  if (G.per[0] && n <= 3) {
+    R.xb0 = n;
+    R.nxp = 1;
+    R.across = true;
+  } else if (xh >= xl) {
+    const int a0 = cx + xl, b0 = cx + xh + 1;  // [a0, b0), may leave [0, n) on a periodic axis
+    if (a0 < 0) {
+      R.xa0 = 0; R.xb0 = b0; R.xa1 = a0 + n; R.xb1 = n; R.nxp = 2;
+      R.across = true;
+    } else if (b0 > n) {
+      R.xa0 = a0; R.xb0 = n; R.xa1 = 0; R.xb1 = b0 - n; R.nxp = 2;
+      R.across = true;
+    } else {
+      R.xa0 = a0; R.xb0 = b0; R.nxp = 1;
     }
   }
-  bool across = G.per[1] && (G.n[1] <= 3 || cy + yl < 0 || cy + yh >= G.n[1]);
-  for (int o = zl; o <= zh; ++o) lz[nzl++] = cz + o;  // z never wraps
-  {
-    const int n = G.n[0];
-    if (G.per[0] && n <= 3) {
-      xa[0] = 0; xb[0] = n; nxp = 1;
-      across = true;
-    } else if (xh >= xl) {
-      const int a0 = cx + xl, b0 = cx + xh + 1;  // [a0, b0), may leave [0, n) on a periodic axis
-      if (a0 < 0) {
-        xa[0] = 0; xb[0] = b0; xa[1] = a0 + n; xb[1] = n; nxp = 2;
-      } else if (b0 > n) {
-        xa[0] = a0; xb[0] = n; xa[1] = 0; xb[1] = b0 - n; nxp = 2;
-      } else {
-        xa[0] = a0; xb[0] = b0; nxp = 1;
-      }
-    }
-  }
+}
+
+// Cell-list bounds [q0, q1) of the nine rows of x piece p (empty rows
+// [0, 0)).
+LPR_DEV_INLINE void row_piece(const DevBufs& d, const LevelGrid& G, const RowSet& R, int p, uint32_t q0[9],
+                              uint32_t q1[9]) {
+  const int xa = p ? R.xa1 : R.xa0, xb = p ? R.xb1 : R.xb0;
 #pragma unroll
-  for (int r = 0; r < 18; ++r) {
-    const int p = r / 9, a = (r % 9) / 3, b = r % 3;
+  for (int r = 0; r < 9; ++r) {
+    const int a = r / 3, b = r % 3;
     q0[r] = 0u;
     q1[r] = 0u;
-    if (a < nzl && b < nyl && p < nxp) {
-      const int64_t rb = G.base + ((int64_t)lz[a] * G.n[1] + ly[b]) * G.n[0];
-      q0[r] = d.cell_start[rb + xa[p]];
-      q1[r] = d.cell_start[rb + xb[p]];
+    if (a < R.nzl && b < R.nyl && p < R.nxp) {
+      int y = R.y0 + b;
+      if (G.per[1]) y = (y < 0) ? y + G.n[1] : (y >= G.n[1] ? y - G.n[1] : y);
+      const int64_t rb = G.base + ((int64_t)(R.z0 + a) * G.n[1] + y) * G.n[0];
+      q0[r] = d.cell_start[rb + xa];
+      q1[r] = d.cell_start[rb + xb];
     }
   }
-  return across || nxp == 2;
 }
 
 // First pass over one level's rows (the row table holds nr packed rows):
@@ -388,6 +413,17 @@ LPR_DEV_INLINE void walk_rows(const float4* __restrict__ cpf, const uint32_t (*r
       }
     }
   }
+}
+
+// Whether a coarser level has a centre within `reach` of the particle's
+// height (its extents are FP32 roundings: widened by one FP32 ulp).
+LPR_DEV_INLINE bool level_in_reach(const DevBufs& d, int gl, const double4& pi, double reach) {
+  const uint32_t khi = d.zext[2 * gl], klo = d.zext[2 * gl + 1];
+  if (khi == 0u) return false;  // no particle at this level
+  const float fhi = ord_val(khi), flo = -ord_val(klo);
+  const double zhi = (double)fhi + ((double)fabsf(fhi) * 0x1p-23 + 0x1p-126);
+  const double zlo = (double)flo - ((double)fabsf(flo) * 0x1p-23 + 0x1p-126);
+  return pi.z - zhi < reach && zlo - pi.z < reach;
 }
 
 // Owner rule (the smaller radius owns; equal radii, the smaller stable id)
@@ -453,19 +489,18 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
   for (int lev = lev_i; lev < bc.nlev && np <= PCAP; ++lev) {
     const int gl = bc.lev0 + lev;
     const LevelGrid G = d.levels[gl];
-    if (lev > lev_i) {
-      // a coarser level whose particles all sit more than one row away
-      // cannot touch this particle
-      const int zu = row_unclamped(G, pi.z);
-      if (zu < d.zext[2 * gl] - 1 || zu > d.zext[2 * gl + 1] + 1) continue;
-    }
+    if (lev > lev_i && !level_in_reach(d, gl, pi, pi.w + G.rmax + skin)) continue;
     int nr = 0;
-    bool wide = false, across;
-    {
-      uint32_t q0[18], q1[18];
-      across = row_bounds(d, G, pi, pi.w + G.rmax + skin, q0, q1);
+    bool wide = false;
+    RowSet R;
+    row_set(G, pi, pi.w + G.rmax + skin, R);
 #pragma unroll
-      for (int r = 0; r < 18; ++r) {
+    for (int p = 0; p < 2; ++p) {  // compile-time piece index (registers, not scratch)
+      if (p >= R.nxp) break;
+      uint32_t q0[9], q1[9];
+      row_piece(d, G, R, p, q0, q1);
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
         const uint32_t len = q1[r] - q0[r];
         if (len > 0u) {
           wide = wide || len > 63u || q0[r] >= (1u << 26);
@@ -478,7 +513,7 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
       np = PCAP + 1;
       break;
     }
-    if (__any(across))
+    if (__any(R.across))
       walk_rows<true>(d.cpf, rtab, c_idx, t, nr, pfx, pfy, pfz, rif, reach, perx, pery, Lx, Ly, np);
     else
       walk_rows<false>(d.cpf, rtab, c_idx, t, nr, pfx, pfy, pfz, rif, reach, perx, pery, Lx, Ly, np);
@@ -490,18 +525,21 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
     for (int lev = lev_i; lev < bc.nlev; ++lev) {
       const int gl = bc.lev0 + lev;
       const LevelGrid G = d.levels[gl];
-      if (lev > lev_i) {
-        const int zu = row_unclamped(G, pi.z);
-        if (zu < d.zext[2 * gl] - 1 || zu > d.zext[2 * gl + 1] + 1) continue;
+      if (lev > lev_i && !level_in_reach(d, gl, pi, pi.w + G.rmax + skin)) continue;
+      RowSet R;
+      row_set(G, pi, pi.w + G.rmax + skin, R);
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        if (p >= R.nxp) break;
+        uint32_t q0[9], q1[9];
+        row_piece(d, G, R, p, q0, q1);
+        for (int r = 0; r < 9; ++r)
+          for (uint32_t q = q0[r]; q < q1[r]; ++q)
+            if (owner_candidate(bc, pi, si, skin, d.crec[q])) {
+              if (np < PCAP) c_idx[np][t] = (int32_t)q;
+              ++np;
+            }
       }
-      uint32_t q0[18], q1[18];
-      row_bounds(d, G, pi, pi.w + G.rmax + skin, q0, q1);
-      for (int r = 0; r < 18; ++r)
-        for (uint32_t q = q0[r]; q < q1[r]; ++q)
-          if (owner_candidate(bc, pi, si, skin, d.crec[q])) {
-            if (np < PCAP) c_idx[np][t] = (int32_t)q;
-            ++np;
-          }
     }
   }
   // exact pass over the kept candidates, reads four at a time; accepted ones

@@ -675,12 +675,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   e = (hipError_t)(e | hipMemsetAsync(d.stat, 0, sizeof(uint32_t) * 4, st));
   e = (hipError_t)(e | hipMemsetAsync(d.disp, 0, sizeof(float) * N, st));
   e = (hipError_t)(e | hipMemsetAsync(d.viol, 0, sizeof(uint32_t) * 2, st));
-  std::vector<int32_t> hz(2 * levels.size());
-  for (size_t q = 0; q < levels.size(); ++q) {
-    hz[2 * q] = std::numeric_limits<int32_t>::max();
-    hz[2 * q + 1] = std::numeric_limits<int32_t>::min();
-  }
-  e = (hipError_t)(e | up(d.zext, hz.data(), sizeof(int32_t) * hz.size()));
+  e = (hipError_t)(e | hipMemsetAsync(d.zext, 0, sizeof(uint32_t) * 2 * levels.size(), st));
   e = (hipError_t)(e | hipMemsetAsync(d.partial, 0, sizeof(double) * d.nblk * 6 * std::max(1, body_total), st));
   if (b->record) {
     e = (hipError_t)(e | hipMemsetAsync(d.frc, 0, sizeof(float4) * N, st));
