@@ -69,14 +69,18 @@ def counters(d):
 
 def write_trace(src, name, title, args, steps):
     rows = kernel_stats(src)
+    # every step launches the step kernel once, so its calls count the traced
+    # steps (the timed ones and the workload's warm-up)
+    traced = next(c for n, c, a, t, p in rows if n.startswith("k_step"))
     lines = [f"# rocprofv3 kernel trace: {title}",
              "# commands:",
              f"#   {SETTLE}",
              f"#   rocprofv3 --kernel-trace --stats -d <dir> -o run --output-format csv -- {WORK} --steps {steps}{args}",
-             f"# the workload runs a few warm-up steps, then {steps} steps; ms/step = total / {steps}",
+             f"# the trace holds {traced} steps ({steps} timed after the workload's warm-up); "
+             f"ms/step = total / {traced}",
              f"{'kernel':<28}{'calls':>7}{'avg us':>10}{'total ms':>10}{'ms/step':>9}{'share %':>9}"]
     for n, c, a, t, p in rows:
-        lines.append(f"{n:<28}{c:>7}{a:>10.1f}{t:>10.2f}{t / steps:>9.4f}{p:>9.2f}")
+        lines.append(f"{n:<28}{c:>7}{a:>10.1f}{t:>10.2f}{t / traced:>9.4f}{p:>9.2f}")
     with open(os.path.join(PROFILES, name), "w") as f:
         f.write("\n".join(lines) + "\n")
     return {n: a for n, c, a, t, p in rows}
