@@ -1060,27 +1060,48 @@ LPR_DEV_INLINE void make_pose(const WallDef& W, const BodyDef& B, const BodyDyn&
 constexpr int ADV_BS = 1024;
 
 __global__ __launch_bounds__(ADV_BS) void k_advance(DevBufs d, int step_block) {
-  __shared__ double red[ADV_BS];
+  __shared__ double red[ADV_BS / 64][6];
+  __shared__ double tot_s[6];
   if (__syncthreads_or(latched(d.err) ? 1 : 0)) return;  // uniform per block
   const int bed = blockIdx.x;
   const BedConst bc = d.beds[bed];
   const int64_t blk0 = bc.p0 / step_block, blk1 = bc.p1 / step_block;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int b = 0; b < bc.nbody; ++b) {
+    // fixed order: each thread sums its strided partials in ascending block
+    // order (four per component in flight), then the wave's threads by a
+    // shuffle tree, then the waves in ascending order
     double acc[6] = {0, 0, 0, 0, 0, 0};
     const double* part = d.partial + (int64_t)(bc.body0 + b) * 6 * d.nblk;
-    for (int c = 0; c < 6; ++c)
-      for (int64_t q = blk0 + threadIdx.x; q < blk1; q += ADV_BS) acc[c] += part[(int64_t)c * d.nblk + q];
-    double tot[6];
-    for (int c = 0; c < 6; ++c) {
-      red[threadIdx.x] = acc[c];
-      __syncthreads();
-      for (int w = ADV_BS / 2; w >= 1; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
+    for (int64_t q0 = blk0 + threadIdx.x; q0 < blk1; q0 += 4 * ADV_BS) {
+      double v[4][6];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t q = q0 + (int64_t)u * ADV_BS;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[u][c] = (q < blk1) ? part[(int64_t)c * d.nblk + q] : 0.0;
       }
-      tot[c] = red[0];
-      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] += v[u][c];
     }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double sw = wave_sum(acc[c]);
+      if (lane == 0) red[wv][c] = sw;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      double s = 0.0;
+      for (int q = 0; q < ADV_BS / 64; ++q) s += red[q][threadIdx.x];
+      tot_s[threadIdx.x] = s;
+    }
+    __syncthreads();
+    double tot[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tot[c] = tot_s[c];
+    __syncthreads();
     if (threadIdx.x == 0) {
       BodyDyn& D = d.bdyn[bc.body0 + b];
       const BodyDef& B = d.bdefs[bc.body0 + b];
