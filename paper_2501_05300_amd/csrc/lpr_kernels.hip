@@ -258,9 +258,15 @@ void launch_scan(uint32_t* cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipSt
 // from the previous lists.
 
 constexpr int SBS = 64;   // threads per search block
-constexpr int PCAP = 22;  // first-pass candidates kept per particle
-constexpr int RT = 18;    // rows of one level (the row table's length)
-static_assert(RT >= K, "the row table's space also holds the slot sort");
+// One LDS array of LROWS rows per lane, used in three ways:
+//   first pass: rows [0, RT) the row table, rows [RT, LROWS) the kept list;
+//   exact walk (kept list full): rows [LROWS - K, LROWS) its partners;
+//   accepted partners: positions compacted in place in the kept rows, stable
+//   ids in rows [0, K) for the slot sort.
+constexpr int LROWS = 32;
+constexpr int RT = 18;             // a level has at most 9 rows in each of two x pieces
+constexpr int PCAP = LROWS - RT;   // first-pass candidates kept per particle (more: exact walk)
+static_assert(RT >= K && LROWS - K >= K, "sort ids must not overlap a kept list");
 
 // Cells along axis a that can hold a partner closer than `reach` to the
 // coordinate x: the range [c + lo, c + hi] around the particle's cell c, with
@@ -438,13 +444,15 @@ LPR_DEV_INLINE bool owner_candidate(const BedConst& bc, const double4& pi, int32
   return within_skin(d2, pi.w, pj.w, skin);
 }
 
-__global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho) {
-  // per lane: the non-empty rows of the level being walked, packed as
-  // (first cell-list position << 6 | length); once the walk is done the same
-  // space holds the accepted partners' stable ids for the slot sort
-  __shared__ uint32_t rtab[RT][SBS];
-  __shared__ int32_t c_idx[PCAP][SBS];  // kept candidates, then the accepted ones
-  int32_t (*const c_sid)[SBS] = reinterpret_cast<int32_t (*)[SBS]>(rtab);
+// Five waves per SIMD: 8 KB of LDS per 64-lane block and at most ~100 VGPRs
+// (the previous lists' partners are read after the walk to stay within them).
+__global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k_search(DevBufs d, int s, int lo, int ho) {
+  // rows of the level being walked are packed as (first cell-list position
+  // << 6 | length); the rows' layout over the array is described at LROWS
+  __shared__ int32_t lds[LROWS][SBS];
+  uint32_t (*const rtab)[SBS] = reinterpret_cast<uint32_t (*)[SBS]>(lds);
+  int32_t (*const c_sid)[SBS] = lds;
+  int32_t (*c_idx)[SBS] = lds + RT;  // kept candidates, then the accepted ones
   const int t = threadIdx.x;
   // each XCD takes one contiguous range of particles, so the neighbour rows
   // its blocks read overlap in that XCD's L2
@@ -467,12 +475,10 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
   const BedConst bc = d.beds[m >> 8];
   const int lev_i = (int)(m & 0xffu);
   const double4 pi = d.st[s][i].x;
-  // the previous lists, read now so that their latency hides behind the walk
+  // the previous lists' flags and count, read now so that their latency
+  // hides behind the walk
   const uint32_t fo = d.cflag[ho][i];
   const int cnt_old = d.own_cnt[lo][i];
-  int32_t old_j[K];
-#pragma unroll
-  for (int k2 = 0; k2 < K; ++k2) old_j[k2] = (k2 < cnt_old) ? d.own_idx[lo][k2 * N + i] : -1;
   const float rif = (float)pi.w;
   const int32_t si = d.sid[i];
   const double skin = (double)bc.skin;
@@ -518,9 +524,12 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
     else
       walk_rows<false>(d.cpf, rtab, c_idx, t, nr, pfx, pfy, pfz, rif, reach, perx, pery, Lx, Ly, np);
   }
-  if (np > PCAP) {
+  const bool exact = np > PCAP;
+  if (exact) {
     // more kept candidates than the list holds: exact walk from the FP64
-    // records (a dense cluster; the capacity check below still applies)
+    // records into K rows (a dense cluster; the capacity check below still
+    // applies)
+    c_idx = lds + (LROWS - K);
     np = 0;
     for (int lev = lev_i; lev < bc.nlev; ++lev) {
       const int gl = bc.lev0 + lev;
@@ -536,16 +545,20 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
         for (int r = 0; r < 9; ++r)
           for (uint32_t q = q0[r]; q < q1[r]; ++q)
             if (owner_candidate(bc, pi, si, skin, d.crec[q])) {
-              if (np < PCAP) c_idx[np][t] = (int32_t)q;
+              if (np < K) c_idx[np][t] = (int32_t)q;
               ++np;
             }
       }
     }
   }
+  // the previous lists' partners, read alongside the exact pass
+  int32_t old_j[K];
+#pragma unroll
+  for (int k2 = 0; k2 < K; ++k2) old_j[k2] = (k2 < cnt_old) ? d.own_idx[lo][k2 * N + i] : -1;
   // exact pass over the kept candidates, reads four at a time; accepted ones
   // are compacted in place
   int cnt = 0;
-  const int nk = min(np, PCAP);
+  const int nk = min(np, exact ? K : PCAP);
   for (int a = 0; a < nk; a += 4) {
     CRec c[4];
     int32_t qv[4];
@@ -564,7 +577,7 @@ __global__ __launch_bounds__(SBS) void k_search(DevBufs d, int s, int lo, int ho
         ++cnt;
       }
   }
-  if (np > PCAP) cnt = max(cnt, K + 1);  // more partners than slots
+  if (exact && np > K) cnt = max(cnt, K + 1);  // more partners than slots
   if (cnt > K) {
     atomicOr(d.err, ERR_CAPACITY);
     cnt = K;

@@ -1,5 +1,6 @@
 """Edge cases of the HIP stepper: a lone sphere, rejected descriptions, a
-particle with more partners than slots, coincident spheres (GPU)."""
+particle with more partners than slots and one with exactly as many,
+coincident spheres (GPU)."""
 import math
 
 import numpy as np
@@ -85,6 +86,33 @@ def test_more_partners_than_slots_latches_capacity():
         bed.sync()
     x, _, _ = bed.state()  # the state stays readable
     assert np.all(np.isfinite(x))
+
+
+def test_exactly_as_many_partners_as_slots():
+    """A 1 mm sphere overlapped by 16 spheres of 2 mm owns exactly its 16
+    slots: no capacity fault, and the step matches the oracle (the larger
+    spheres also press into one another)."""
+    from paper_2501_05300_amd.lprdem import Bed
+    c = np.array([0.05, 0.05, 0.05])
+    golden = math.pi * (3.0 - math.sqrt(5.0))
+    pts = []
+    for q in range(16):  # Fibonacci points on a sphere of radius 2.9 mm
+        z = 1.0 - 2.0 * (q + 0.5) / 16
+        rr = math.sqrt(1.0 - z * z)
+        pts.append(c + 2.9e-3 * np.array([rr * math.cos(golden * q), rr * math.sin(golden * q), z]))
+    spec = spec_of([c] + pts, [1e-3] + [2e-3] * 16, params=beds.paper_params(E=1e6))
+    bed = Bed(spec, record_forces=True)
+    res = compare_one_step(spec, bed)
+    bed.sync()  # raises if a fault latched
+    print({k: v for k, v in res.items() if k not in ("only_gpu", "only_oracle")})
+    assert res["contacts_equal"], res
+    got = bed.contacts()
+    assert int(np.sum(got[:, 0] == 0)) == 16  # stable id 0 is the small sphere
+    assert res["force_rel"] < 1e-5
+    # from rest there is no tangential motion, so the torques vanish up to
+    # rounding: compare them with the force scale times the lever arm
+    F, T = bed.forces()
+    assert float(np.abs(T).max()) <= 1e-5 * float(np.abs(F).max()) * 2e-3
 
 
 def test_coincident_spheres_match_oracle():
