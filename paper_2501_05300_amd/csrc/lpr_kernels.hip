@@ -403,9 +403,12 @@ LPR_DEV_INLINE void walk_rows(const float4* __restrict__ cpf, const uint32_t (*r
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) c[u] = cpf[ok[u] ? qa[u] : qa[0]];
+    // the test is evaluated for all eight without branching, so each
+    // candidate stays one 16-byte read (a branch on the radius first would
+    // let the compiler fetch the position only after it)
+    bool keep[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      if (!ok[u] || c[u].w < rif) continue;  // j owns pairs with a smaller radius
       float fx = c[u].x - pfx, fy = c[u].y - pfy;
       const float fz = c[u].z - pfz;
       if (WRAP) {
@@ -413,11 +416,15 @@ LPR_DEV_INLINE void walk_rows(const float4* __restrict__ cpf, const uint32_t (*r
         if (pery) fy = (fy > 0.5f * Ly) ? fy - Ly : ((fy < -0.5f * Ly) ? fy + Ly : fy);
       }
       const float Rf = reach + c[u].w;
-      if (fx * fx + fy * fy + fz * fz < Rf * Rf) {
+      // j owns pairs with a smaller radius
+      keep[u] = ok[u] && !(c[u].w < rif) && (fx * fx + fy * fy + fz * fz < Rf * Rf);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (keep[u]) {
         if (np < PCAP) c_idx[np][t] = (int32_t)qa[u];
         ++np;
       }
-    }
   }
 }
 
