@@ -376,13 +376,15 @@ template <bool WRAP>
 LPR_DEV_INLINE void walk_rows(const float4* __restrict__ cpf, const uint32_t (*rtab)[SBS], int32_t (*c_idx)[SBS], int t,
                               int nr, float pfx, float pfy, float pfz, float rif, float reach, bool perx, bool pery,
                               float Lx, float Ly, int& np) {
-  // at the top of a round position q lies in row ri
+  // at the top of a round position q lies in row ri; the next row's entry
+  // is held in wn, so that moving on to it waits for no LDS read
   int ri = 0;
-  uint32_t q = 0u, e = 0u;
+  uint32_t q = 0u, e = 0u, wn = 0u;
   if (nr > 0) {
     const uint32_t w = rtab[0][t];
     q = w >> 6;
     e = q + (w & 63u);
+    if (nr > 1) wn = rtab[1][t];
   }
   while (ri < nr) {
     float4 c[8];
@@ -394,11 +396,9 @@ LPR_DEV_INLINE void walk_rows(const float4* __restrict__ cpf, const uint32_t (*r
       qa[u] = q;
       if (ok[u] && ++q >= e) {
         ++ri;
-        if (ri < nr) {
-          const uint32_t w = rtab[ri][t];
-          q = w >> 6;
-          e = q + (w & 63u);
-        }
+        q = wn >> 6;
+        e = q + (wn & 63u);
+        if (ri + 1 < nr) wn = rtab[ri + 1][t];
       }
     }
 #pragma unroll
