@@ -211,6 +211,54 @@ def adjoint_leg(n, window, ckpt, settle, pre, seed=0):
             "adjoint_over_forward_every_step": t_adj / t_plain, "adjoint_over_forward_skin": t_adj / t_skin}
 
 
+def configs_leg(steps_c2, steps_c3, warmup, settle):
+    """The survey's other workloads on the plain stepper (every-step search):
+    a 200k graded bed under a 0.1 m plate pushed at 0.01 m/s, and the
+    grousered ring (5 kPa dead weight, 0.5 rad/s) on a 2.0M uniform bed and
+    on a 150k graded bed (k = 2, L = 0.105 m) in the same 0.4 m box, whose
+    particle-count and per-step cost ratios are the refinement's saving."""
+    import numpy as np
+    import torch
+    from paper_2501_05300_amd import beds
+    from paper_2501_05300_amd.lprdem import Bed
+    c2 = beds.graded_bed(200_000, seed=0)
+    c3c = beds.uniform_bed(2_000_000, r=1.5e-3, depth=0.2805, side=0.4, seed=0)
+    c3g = beds.graded_bed(150_000, r0=1.5e-3, L=0.105, k=2.0, cap=8.0, depth=0.2805, side=0.4, seed=0)
+    settle_beds([c2, c3c, c3g], settle)
+    beds.add_plate(c2, diameter=0.1, speed=0.01)
+    beds.add_ring(c3c)
+    beds.add_ring(c3g)
+    out = {}
+    for name, spec, steps in (("plate_200k_graded", c2, steps_c2), ("ring_2M_uniform_control", c3c, steps_c3),
+                              ("ring_150k_graded", c3g, steps_c3)):
+        body = spec.info["plate_body"]
+        bed = Bed(spec)
+        bed.step(warmup)
+        bed.sync()
+        z0 = float(bed.body(body)[0][2])
+        bed.reaction_window(body, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prof = bed.step_profiled(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = bed.stats()
+        sum6, nsum = bed.reaction_window(body)
+        out[name] = {"n": spec.n, "steps": steps, "ms_per_step": 1e3 * wall / steps,
+                     "particle_steps_per_s": spec.n * steps / wall,
+                     "contacts_per_s": st["contacts"] * steps / wall,
+                     "contacts_per_particle": st["contacts"] / spec.n,
+                     "kernel_ms_per_step": {k: v / steps for k, v in prof.items()},
+                     "mean_body_reaction_z_N": float(sum6[2]) / max(nsum, 1),
+                     "body_sinkage_m": z0 - float(bed.body(body)[0][2])}
+        log(f"{name}: {out[name]['ms_per_step']:.3f} ms/step, {out[name]['particle_steps_per_s']:.3e} particle-steps/s")
+        bed.close()
+    c, g = out["ring_2M_uniform_control"], out["ring_150k_graded"]
+    out["ring_count_ratio_control_over_graded"] = c["n"] / g["n"]
+    out["ring_step_cost_ratio_control_over_graded"] = c["ms_per_step"] / g["ms_per_step"]
+    return out
+
+
 def cpu_baseline(spec, pos, vel, omg, keys, vals, clock, steps):
     """The FP64 oracle, as it stands, on the same bed state (bounded sample:
     `steps` steps of the full bed)."""
@@ -247,6 +295,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=300, help="timed steps of the 36-bed leg (0: skip)")
     ap.add_argument("--batch-settle", type=int, default=40000)
     ap.add_argument("--adjoint-window", type=int, default=2000, help="steps of the adjoint leg (0: skip)")
+    ap.add_argument("--configs", action="store_true",
+                    help="also time the plate (200k graded) and grousered-ring (2.0M uniform vs 150k graded) beds")
     ap.add_argument("--settle", type=int, default=40000,
                     help="relaxation steps before the measurement (paper's reduced friction, damped, dt 5e-6)")
     args = ap.parse_args()
@@ -356,6 +406,8 @@ def main():
         out["batched"] = batch_leg(args.batch_steps, 100, args.batch_settle, 10)
     if args.adjoint_window > 0:
         out["adjoint"] = adjoint_leg(50_000, args.adjoint_window, 100, args.settle, 50_000, args.seed)
+    if args.configs:
+        out["other_configs"] = configs_leg(20_000, 10_000, 200, args.settle)
     print(json.dumps(out), flush=True)
 
 
