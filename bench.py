@@ -366,6 +366,12 @@ def main():
                      "kernel": "k_step (fused narrow phase, law, accumulation, walls, integration)",
                      "bytes_per_particle_step": b_alg, "algorithmic_bytes_per_launch": N * b_alg},
         "algorithmic_frac_whole_step": N * b_alg / (wall / args.steps) / 1e9 / HBM_PEAK_GBS,
+        "paper_context": {
+            "absolute_throughput_reported": False,
+            "relative": "refined beds ran 3.1x to 43.0x faster than the 305k-sphere uniform reference bed "
+                        "(2.3x to 25x fewer particles, fewer Gauss-Seidel iterations); implicit CPU solver, "
+                        "hardware and precision not stated (abstract; results on simulation speed)",
+        },
     }
     if args.secondary_every > 1:
         bed.close()
