@@ -372,37 +372,67 @@ LPR_DEV_INLINE void row_piece(const DevBufs& d, const LevelGrid& G, const RowSet
 // larger radius owns nothing here).  WRAP takes the minimum image on the
 // periodic axes; a wave whose lanes have no cell across a periodic edge
 // skips it, since then every separation is already the nearest image.
+// a if c, else b, as bit masks (a plain conditional here would be turned into
+// control flow)
+LPR_DEV_INLINE uint32_t pick(bool c, uint32_t a, uint32_t b) {
+  const uint32_t m = 0u - (uint32_t)c;
+  return (a & m) | (b & ~m);
+}
+
 template <bool WRAP>
 LPR_DEV_INLINE void walk_rows(const float4* __restrict__ cpf, const uint32_t (*rtab)[SBS], int32_t (*c_idx)[SBS], int t,
                               int nr, float pfx, float pfy, float pfz, float rif, float reach, bool perx, bool pery,
                               float Lx, float Ly, int& np) {
-  // at the top of a round position q lies in row ri; the next row's entry
-  // is held in wn, so that moving on to it waits for no LDS read
+  if (nr <= 0) return;
+  // rows ri, ri + 1, ri + 2 as packed entries; row ri's unread part is
+  // [qa0, qa0 + la), never empty.  Entries past nr are read (they lie inside
+  // the LDS array) but never used.
   int ri = 0;
-  uint32_t q = 0u, e = 0u, wn = 0u;
-  if (nr > 0) {
-    const uint32_t w = rtab[0][t];
-    q = w >> 6;
-    e = q + (w & 63u);
-    if (nr > 1) wn = rtab[1][t];
+  uint32_t wb = rtab[1][t], wc = rtab[2][t];
+  uint32_t qa0, la;
+  {
+    const uint32_t wa = rtab[0][t];
+    qa0 = wa >> 6;
+    la = wa & 63u;
   }
   while (ri < nr) {
     float4 c[8];
     uint32_t qa[8];
     bool ok[8];
+    // positions of the round without branches: the rest of row ri, then
+    // rows ri + 1 and ri + 2 (a round ends early where it would need a
+    // fourth row)
+    const int avA = (int)la;
+    const int avB = (ri + 1 < nr) ? (int)(wb & 63u) : 0;
+    const int avC = (ri + 2 < nr) ? (int)(wc & 63u) : 0;
+    const uint32_t qb0 = wb >> 6, qc0 = wc >> 6;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      ok[u] = ri < nr;
-      qa[u] = q;
-      if (ok[u] && ++q >= e) {
-        ++ri;
-        q = wn >> 6;
-        e = q + (wn & 63u);
-        if (ri + 1 < nr) wn = rtab[ri + 1][t];
-      }
+      const int ub = u - avA, uc = ub - avB;
+      qa[u] = pick(u < avA, qa0 + (uint32_t)u, pick(ub < avB, qb0 + (uint32_t)ub, qc0 + (uint32_t)uc));
+      ok[u] = uc < avC;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) c[u] = cpf[ok[u] ? qa[u] : qa[0]];
+    for (int u = 0; u < 8; ++u) c[u] = cpf[pick(ok[u], qa[u], qa0)];
+    {
+      // move past the rows this round used up (their LDS entries are read
+      // while the candidates are in flight)
+      const int s1 = avA, s2 = avA + avB, s3 = s2 + avC;
+      const int used = min(8, s3);
+      const int k = (used >= s1 ? 1 : 0) + (used >= s2 && ri + 1 < nr ? 1 : 0) + (used >= s3 && ri + 2 < nr ? 1 : 0);
+      if (k == 0) {
+        qa0 += (uint32_t)used;
+        la -= (uint32_t)used;
+      } else {
+        const int off = used - (k == 1 ? s1 : (k == 2 ? s2 : s3));
+        ri += k;
+        const uint32_t wa = rtab[ri][t];
+        wb = rtab[ri + 1][t];
+        wc = rtab[ri + 2][t];
+        qa0 = (wa >> 6) + (uint32_t)off;
+        la = (wa & 63u) - (uint32_t)off;
+      }
+    }
     // the test is evaluated for all eight without branching, so each
     // candidate stays one 16-byte read (a branch on the radius first would
     // let the compiler fetch the position only after it)
@@ -416,8 +446,8 @@ LPR_DEV_INLINE void walk_rows(const float4* __restrict__ cpf, const uint32_t (*r
         if (pery) fy = (fy > 0.5f * Ly) ? fy - Ly : ((fy < -0.5f * Ly) ? fy + Ly : fy);
       }
       const float Rf = reach + c[u].w;
-      // j owns pairs with a smaller radius
-      keep[u] = ok[u] && !(c[u].w < rif) && (fx * fx + fy * fy + fz * fz < Rf * Rf);
+      // j owns pairs with a smaller radius (bitwise and: no short circuit)
+      keep[u] = ok[u] & !(c[u].w < rif) & (fx * fx + fy * fy + fz * fz < Rf * Rf);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
