@@ -259,13 +259,14 @@ void launch_scan(uint32_t* cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipSt
 
 constexpr int SBS = 64;   // threads per search block
 // One LDS array of LROWS rows per lane, used in three ways:
-//   first pass: rows [0, RT) the row table, rows [RT, LROWS) the kept list;
+//   first pass: rows [0, RT) the row table, rows [RT, LROWS - 1) the kept
+//   list and row LROWS - 1 a sink for the writes that keep nothing;
 //   exact walk (kept list full): rows [LROWS - K, LROWS) its partners;
 //   accepted partners: positions compacted in place in the kept rows, stable
 //   ids in rows [0, K) for the slot sort.
 constexpr int LROWS = 32;
 constexpr int RT = 18;             // a level has at most 9 rows in each of two x pieces
-constexpr int PCAP = LROWS - RT;   // first-pass candidates kept per particle (more: exact walk)
+constexpr int PCAP = LROWS - RT - 1;  // first-pass candidates kept per particle (more: exact walk)
 static_assert(RT >= K && LROWS - K >= K, "sort ids must not overlap a kept list");
 
 // Cells along axis a that can hold a partner closer than `reach` to the
@@ -449,12 +450,14 @@ LPR_DEV_INLINE void walk_rows(const float4* __restrict__ cpf, const uint32_t (*r
       // j owns pairs with a smaller radius (bitwise and: no short circuit)
       keep[u] = ok[u] & !(c[u].w < rif) & (fx * fx + fy * fy + fz * fz < Rf * Rf);
     }
+    // every slot writes (no branches): a slot that keeps nothing writes the
+    // next free entry, which a kept one overwrites, or the sink row once the
+    // list is full
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (keep[u]) {
-        if (np < PCAP) c_idx[np][t] = (int32_t)qa[u];
-        ++np;
-      }
+    for (int u = 0; u < 8; ++u) {
+      c_idx[min(np, PCAP)][t] = (int32_t)qa[u];
+      np += keep[u] ? 1 : 0;
+    }
   }
 }
 
