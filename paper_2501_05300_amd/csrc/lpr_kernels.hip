@@ -242,20 +242,19 @@ void launch_scan(uint32_t* cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipSt
 // owner-side search with history carry-over
 //
 // Each thread walks the neighbourhood of its particle at its own level and
-// every coarser one (a coarser level only when its occupied rows reach the
-// particle's row): along each axis the particle's cell and those of its two
-// neighbours that lie within r_i + r_max(level) + skin of it.  That is at
+// every coarser one (a coarser level only when its recorded centre heights
+// lie within reach): along each axis the particle's cell and those of its
+// two neighbours that lie within r_i + r_max(level) + skin of it.  That is at
 // most 3 x 3 rows of up to 3 cells; the cells of a row are consecutive in
 // the cell order, so the row is one range of the cell lists (two where the x
-// axis wraps).  All 18 range bounds are loaded before the first candidate.
-// A first pass reads the 16-byte FP32 copy of each candidate, eight per
-// round (a round that passes the end of a row continues into the next), and
-// keeps the
-// ones within a conservative FP32 distance bound (and not owned by the
-// partner); a second pass reads the kept candidates' FP64 records, four at a
-// time, and applies the owner rule and the exact predicate.  Accepted
-// partners are put in ascending stable id and inherit their spring history
-// from the previous lists.
+// axis wraps).  The bounds of a piece's nine rows are read together and the
+// non-empty rows packed into a per-lane LDS table.  A first pass reads the
+// 16-byte FP32 copy of each candidate, eight per round in one stream over
+// the table's rows, and keeps the ones within a conservative FP32 distance
+// bound (and not owned by the partner); a second pass reads the kept
+// candidates' FP64 records, four at a time, and applies the owner rule and
+// the exact predicate.  Accepted partners are put in ascending stable id and
+// inherit their spring history from the previous lists.
 
 constexpr int SBS = 64;   // threads per search block
 // One LDS array of LROWS rows per lane, used in three ways:
@@ -366,13 +365,6 @@ LPR_DEV_INLINE void row_piece(const DevBufs& d, const LevelGrid& G, const RowSet
   }
 }
 
-// First pass over one level's rows (the row table holds nr packed rows):
-// each lane walks its rows as one stream, eight positions per round, so its
-// rounds follow its own candidate count, and keeps the candidates that pass
-// a conservative FP32 distance bound and are not owned by the partner (a
-// larger radius owns nothing here).  WRAP takes the minimum image on the
-// periodic axes; a wave whose lanes have no cell across a periodic edge
-// skips it, since then every separation is already the nearest image.
 // a if c, else b, as bit masks (a plain conditional here would be turned into
 // control flow)
 LPR_DEV_INLINE uint32_t pick(bool c, uint32_t a, uint32_t b) {
@@ -380,6 +372,13 @@ LPR_DEV_INLINE uint32_t pick(bool c, uint32_t a, uint32_t b) {
   return (a & m) | (b & ~m);
 }
 
+// First pass over one level's rows (the row table holds nr packed rows):
+// each lane walks its rows as one stream, eight positions per round, so its
+// rounds follow its own candidate count, and keeps the candidates that pass
+// a conservative FP32 distance bound and are not owned by the partner (a
+// larger radius owns nothing here).  WRAP takes the minimum image on the
+// periodic axes; a wave whose lanes have no cell across a periodic edge
+// skips it, since then every separation is already the nearest image.
 template <bool WRAP>
 LPR_DEV_INLINE void walk_rows(const float4* __restrict__ cpf, const uint32_t (*rtab)[SBS], int32_t (*c_idx)[SBS], int t,
                               int nr, float pfx, float pfy, float pfz, float rif, float reach, bool perx, bool pery,

@@ -18,6 +18,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 from collections import defaultdict
 
@@ -36,12 +37,21 @@ B_PARTICLE = 100.0
 B_PAIR = 56.0
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and whitespace (string literals in these
+    files hold no comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return re.sub(r"\s+", "", text)
+
+
 def kernel_source_hash() -> str:
-    """Hash of the device sources; a counter record is valid only for it."""
+    """Hash of the device code (comments and layout ignored); a counter
+    record is valid only for it."""
     h = hashlib.sha256()
     for f in ("lpr_dev.h", "lpr_kernels.hip"):
-        with open(os.path.join(ROOT, "paper_2501_05300_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2501_05300_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
