@@ -41,18 +41,19 @@ def log(msg):
 
 
 def counter_traffic(n_particles):
-    """HBM bytes per launch of the step kernel (every-step search, skin lists)
-    from the committed rocprofv3 counter record, when it was taken on the
-    current kernel source; otherwise (None, None)."""
+    """HBM bytes per launch of the step kernel and per whole step (every-step
+    search, skin lists) from the committed rocprofv3 counter record, when it
+    was taken on the current kernel code; otherwise Nones."""
     from paper_2501_05300_amd.profile_summary import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "step_kernel_counters_metric_bed.json")
     if not os.path.exists(path):
-        return None, None
+        return None, None, None, None
     with open(path) as f:
         c = json.load(f)
     if c.get("kernel_source_hash") != kernel_source_hash() or c.get("n") != n_particles:
-        return None, None
-    return c.get("hbm_bytes_per_launch"), c.get("hbm_bytes_per_launch_skin_lists")
+        return None, None, None, None
+    return (c.get("hbm_bytes_per_launch"), c.get("hbm_bytes_per_launch_skin_lists"), c.get("hbm_bytes_per_step"),
+            c.get("hbm_bytes_per_step_skin_lists"))
 
 
 def settle_beds(specs, steps, chunk=5000):
@@ -338,7 +339,7 @@ def main():
     step_ms = prof["step"] / args.steps
     b_alg = B_PARTICLE + B_PAIR * cbar
     achieved = N * b_alg / (step_ms * 1e-3) / 1e9
-    traffic, traffic_skin = counter_traffic(N)
+    traffic, traffic_skin, step_bytes, step_bytes_skin = counter_traffic(N)
     out = {
         "metric": METRIC,
         "value": value,
@@ -366,6 +367,7 @@ def main():
                      "kernel": "k_step (fused narrow phase, law, accumulation, walls, integration)",
                      "bytes_per_particle_step": b_alg, "algorithmic_bytes_per_launch": N * b_alg},
         "algorithmic_frac_whole_step": N * b_alg / (wall / args.steps) / 1e9 / HBM_PEAK_GBS,
+        "counter_frac_whole_step": (step_bytes / (wall / args.steps) / 1e9 / HBM_PEAK_GBS) if step_bytes else None,
         "paper_context": {
             "absolute_throughput_reported": False,
             "relative": "refined beds ran 3.1x to 43.0x faster than the 305k-sphere uniform reference bed "
@@ -399,6 +401,8 @@ def main():
             "step_kernel_traffic": traffic_skin,
             "step_kernel_traffic_frac": traffic_skin / (step2 * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic_skin else None,
             "algorithmic_frac_whole_step": N * b2 / (wall2 / args.steps) / 1e9 / HBM_PEAK_GBS,
+            "counter_frac_whole_step": (step_bytes_skin / (wall2 / args.steps) / 1e9 / HBM_PEAK_GBS
+                                        if step_bytes_skin else None),
         }
     if args.cpu_steps > 0:
         pos, vel, omg = bed.state()

@@ -93,7 +93,7 @@ def write_trace(src, name, title, args, steps):
         lines.append(f"{n:<28}{c:>7}{a:>10.1f}{t:>10.2f}{t / traced:>9.4f}{p:>9.2f}")
     with open(os.path.join(PROFILES, name), "w") as f:
         f.write("\n".join(lines) + "\n")
-    return {n: a for n, c, a, t, p in rows}
+    return {n: a for n, c, a, t, p in rows}, {n: c / traced for n, c, a, t, p in rows}
 
 
 def scales(fetch, write):
@@ -135,9 +135,9 @@ def write_traffic(fdir, wdir, avg_us, name, title, args, cbar):
 
 def main(src, cbar_every=2.42, cbar_skin=2.42):
     os.makedirs(PROFILES, exist_ok=True)
-    every = write_trace(os.path.join(src, "trace_every"), "kernels_metric_bed_every_step.txt",
-                        "settled 2,000,000-sphere graded bed, cell search every step", "", 100)
-    skin = write_trace(os.path.join(src, "trace_skin"), "kernels_metric_bed_skin_lists.txt",
+    every, calls_e = write_trace(os.path.join(src, "trace_every"), "kernels_metric_bed_every_step.txt",
+                                 "settled 2,000,000-sphere graded bed, cell search every step", "", 100)
+    skin, calls_s = write_trace(os.path.join(src, "trace_skin"), "kernels_metric_bed_skin_lists.txt",
                        "settled 2,000,000-sphere graded bed, candidate lists with a skin rebuilt every 50 steps",
                        " " + SKIN_ARGS, 200)
     rec_e, sf, sw = write_traffic(os.path.join(src, "fetch_every"), os.path.join(src, "write_every"), every,
@@ -147,9 +147,16 @@ def main(src, cbar_every=2.42, cbar_skin=2.42):
                                 "hbm_traffic_metric_bed_skin_lists.txt",
                                 "settled 2,000,000-sphere graded bed, skin lists", " " + SKIN_ARGS, cbar_skin)
     step = next(k for k in rec_e if k.startswith("k_step"))
+
+    def per_step(rec, calls):
+        # HBM bytes of every kernel of the step, weighted by launches per step
+        return sum((r["fetch_bytes"] + r["write_bytes"]) * calls.get(k, 0.0) for k, r in rec.items())
+
     out = {"kernel_source_hash": kernel_source_hash(), "n": N_METRIC, "kernel": step,
            "hbm_bytes_per_launch": rec_e[step]["fetch_bytes"] + rec_e[step]["write_bytes"],
            "hbm_bytes_per_launch_skin_lists": rec_s[step]["fetch_bytes"] + rec_s[step]["write_bytes"],
+           "hbm_bytes_per_step": per_step(rec_e, calls_e),
+           "hbm_bytes_per_step_skin_lists": per_step(rec_s, calls_s),
            "fetch_scale": sf, "write_scale": sw,
            "every_step": rec_e, "skin_lists": rec_s,
            "source": "profiles/hbm_traffic_metric_bed_every_step.txt, profiles/hbm_traffic_metric_bed_skin_lists.txt"}

@@ -1,6 +1,6 @@
 """Edge cases of the HIP stepper: a lone sphere, rejected descriptions, a
-particle with more partners than slots and one with exactly as many,
-coincident spheres (GPU)."""
+particle with more partners than slots and one with exactly as many, cells
+too crowded for the search's row table, coincident spheres (GPU)."""
 import math
 
 import numpy as np
@@ -113,6 +113,34 @@ def test_exactly_as_many_partners_as_slots():
     # rounding: compare them with the force scale times the lever arm
     F, T = bed.forces()
     assert float(np.abs(T).max()) <= 1e-5 * float(np.abs(F).max()) * 2e-3
+
+
+def test_crowded_cells_take_the_exact_walk():
+    """One radius band spanning a factor 8 (band ratio 8): a cell of the
+    2.2 mm spheres' size holds hundreds of 0.3 mm spheres, so every row of
+    cells is longer than the search's packed row table takes and every lane
+    walks the FP64 records instead; the large spheres also collect hundreds
+    of partner-side entries.  Contacts, forces and torques match the oracle."""
+    import numpy as np
+    from paper_2501_05300_amd.lprdem import Bed
+    rng = np.random.default_rng(11)
+    n_small, n_large, side, height = 8000, 6, 0.012, 0.008
+    pos = np.stack([rng.uniform(0, side, n_small + n_large), rng.uniform(0, side, n_small + n_large),
+                    rng.uniform(0, height, n_small + n_large)], 1)
+    radius = np.concatenate([rng.uniform(0.28e-3, 0.32e-3, n_small), np.full(n_large, 2.2e-3)])
+    spec = spec_of(pos, radius, box=(side, side, 0.0), periodic=3, params=beds.paper_params(E=1e6))
+    bed = Bed(spec, record_forces=True, band_ratio=8.0)
+    res = compare_one_step(spec, bed)
+    bed.sync()
+    print({k: v for k, v in res.items() if k not in ("only_gpu", "only_oracle")})
+    assert res["contacts_equal"], res
+    got = bed.contacts()
+    large = np.arange(n_small, n_small + n_large)
+    assert int(np.isin(got[:, 1], large).sum()) > 100 * n_large  # long partner-side lists
+    assert res["force_rel"] < 1e-5
+    # from rest the torques vanish up to rounding (see above)
+    F, T = bed.forces()
+    assert float(np.abs(T).max()) <= 1e-5 * float(np.abs(F).max()) * 2.2e-3
 
 
 def test_coincident_spheres_match_oracle():
