@@ -158,12 +158,14 @@ typedef struct {
 
 typedef struct lpr_bed lpr_bed;
 
-/* Creates a bed.  The description is validated (n > 0, r > 0, finite
- * inputs, dt > 0, periodic length > 2 max(r_i + r_j + skin), wall/body
- * indices in range), particles are placed in Morton order per radius band
- * on the device, and the per-step kernel sequence is captured in a HIP
- * graph on `hip_stream` (NULL = the default stream).  *out receives the bed;
- * on error *out is NULL. */
+/* Creates a bed.  The description is validated (0 < n < 2^27, r > 0,
+ * finite inputs, dt > 0, periodic length > 2 max(r_i + r_j + skin),
+ * wall/body indices in range), particles are placed in Morton order per
+ * radius band on the device, and the per-step kernel sequence is captured in
+ * a HIP graph on `hip_stream` (NULL = the default stream).  *out receives
+ * the bed; on error *out is NULL.  A sphere owns its contacts with spheres
+ * of larger radius (equal radii: larger stable id) in 16 slots; a 17th
+ * latches LPR_E_CAPACITY, reported at the next lpr_sync. */
 lpr_status lpr_bed_create(const lpr_bed_desc* desc, const lpr_allocator* alloc, void* hip_stream,
                           lpr_bed** out);
 lpr_status lpr_bed_destroy(lpr_bed* bed);
