@@ -288,7 +288,8 @@ def main():
     ap.add_argument("--rebuild-every", type=int, default=1)
     ap.add_argument("--skin", type=float, default=0.0)
     ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=3,
+                    help="oracle steps of the full bed for the CPU baseline, about 17 s on 16 cores (0: skip)")
     ap.add_argument("--secondary-every", type=int, default=50,
                     help="also time candidate lists with a skin rebuilt every k steps (0: skip)")
     ap.add_argument("--secondary-skin", type=float, default=0.05,
