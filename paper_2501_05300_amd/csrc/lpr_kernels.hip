@@ -483,7 +483,7 @@ LPR_DEV_INLINE bool owner_candidate(const BedConst& bc, const double4& pi, int32
   return within_skin(d2, pi.w, pj.w, skin);
 }
 
-// Five waves per SIMD: 8 KB of LDS per 64-lane block and at most ~100 VGPRs
+// Five waves per SIMD: 8 KB of LDS per 64-lane block and at most 96 VGPRs
 // (the previous lists' partners are read after the walk to stay within them).
 __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k_search(DevBufs d, int s, int lo, int ho) {
   // rows of the level being walked are packed as (first cell-list position
