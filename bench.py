@@ -212,6 +212,63 @@ def adjoint_leg(n, window, ckpt, settle, pre, seed=0):
             "adjoint_over_forward_every_step": t_adj / t_plain, "adjoint_over_forward_skin": t_adj / t_skin}
 
 
+def calibration_leg(n, window, ckpt, settle, seed=0):
+    """Bulk calibration with the adjoint on the adjoint leg's 50k graded bed:
+    two plate experiments (a 0.1 m plate pushed at 0.01 and 0.005 m/s until
+    it has sunk 1 mm, then a window of `window` steps each) whose targets
+    are the GPU's own mean plate reactions at theta* = (1.25, 0.36, 0.02);
+    (s_k, mu_t) are fitted from the bed's own (1.0, 0.3) by damped
+    Gauss-Newton, every evaluation one adjoint window per experiment."""
+    import numpy as np
+    import torch
+    from paper_2501_05300_amd import beds
+    from paper_2501_05300_amd.calibrate import Experiment, calibrate
+    from paper_2501_05300_amd.lprdem import Bed
+    base = beds.graded_bed(n, r0=1.5e-3, L=0.02, k=1.0, depth=0.2, seed=seed + 50)
+    if settle > 0:
+        settle_beds([base], settle)
+    skin = 0.25 * float(base.radius.min())
+    exps = []
+    for speed, pre in ((0.01, 50_000), (0.005, 100_000)):
+        spec = beds.add_plate(base.copy(), diameter=0.1, speed=speed)
+        bed = Bed(spec, rebuild_every=10, skin=skin)
+        done = 0
+        while done < pre:
+            k = min(10_000, pre - done)
+            bed.step(k)
+            bed.sync()
+            done += k
+        exps.append(Experiment.from_bed(spec, bed, spec.info["plate_body"], window, ckpt,
+                                        rebuild_every=10, skin=skin))
+        bed.close()
+    log(f"calibration: two plate experiments pushed to 1 mm, windows of {window} steps")
+    theta_star = np.array([1.25, 0.36, 0.02])
+    theta0 = np.array([exps[0].spec.params.s_k, exps[0].spec.params.mu_t, exps[0].spec.params.mu_r])
+    targets = [e.response(theta_star)[0] for e in exps]
+    calls = [0]
+    responses = [e.response for e in exps]
+    for e, f in zip(exps, responses):
+        def counted(th, f=f):
+            calls[0] += 1
+            return f(th)
+        e.response = counted
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    theta, hist = calibrate(exps, targets, theta0, (True, True, False), iters=8)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    for e in exps:
+        e.close()
+    evals = calls[0] // len(exps)
+    log(f"calibration: theta {theta} after {len(hist) - 1} iterates, {evals} evaluations, {t_fit:.2f} s; "
+        f"residuals {[h['residual'] for h in hist]}")
+    return {"spheres": base.n, "window_steps": window, "experiments": len(exps),
+            "targets_N": [float(t) for t in targets], "theta_start": theta0.tolist(), "theta_true": theta_star.tolist(),
+            "theta_fit": theta.tolist(), "max_rel_error": float(np.max(np.abs(theta - theta_star) / theta_star)),
+            "residuals": [h["residual"] for h in hist], "evaluations": evals, "fit_s": t_fit,
+            "s_per_evaluation": t_fit / max(evals, 1)}
+
+
 def configs_leg(steps_c2, steps_c3, warmup, settle):
     """The survey's other workloads on the plain stepper (every-step search):
     a 200k graded bed under a 0.1 m plate pushed at 0.01 m/s, and the
@@ -297,6 +354,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=300, help="timed steps of the 36-bed leg (0: skip)")
     ap.add_argument("--batch-settle", type=int, default=40000)
     ap.add_argument("--adjoint-window", type=int, default=2000, help="steps of the adjoint leg (0: skip)")
+    ap.add_argument("--calibrate-window", type=int, default=2000,
+                    help="steps per experiment of the calibration leg (0: skip)")
     ap.add_argument("--configs", action="store_true",
                     help="also time the plate (200k graded) and grousered-ring (2.0M uniform vs 150k graded) beds")
     ap.add_argument("--settle", type=int, default=40000,
@@ -417,6 +476,8 @@ def main():
         out["batched"] = batch_leg(args.batch_steps, 100, args.batch_settle, 10)
     if args.adjoint_window > 0:
         out["adjoint"] = adjoint_leg(50_000, args.adjoint_window, 100, args.settle, 50_000, args.seed)
+    if args.calibrate_window > 0:
+        out["calibration"] = calibration_leg(50_000, args.calibrate_window, 100, args.settle, args.seed)
     if args.configs:
         out["other_configs"] = configs_leg(20_000, 10_000, 200, args.settle)
     print(json.dumps(out), flush=True)
