@@ -90,8 +90,18 @@ int64_t orc_history_count(const orc_bed* b);
 int orc_get_history(const orc_bed* b, int64_t* keys2, double* vals6, int64_t cap);
 int orc_set_history(orc_bed* b, int64_t count, const int64_t* keys2, const double* vals6);
 
-/* Advances n_steps steps. */
+/* Advances n_steps steps with the bed's stepper. */
 int orc_step(orc_bed* b, int64_t n_steps);
+
+/* Chooses the stepper: kind 0 = explicit compliant step (default); kind 1 =
+ * the time-implicit SPOOK step (section "Nonsmooth DEM and multibody
+ * dynamics") solved with n_iter projected block-Jacobi iterations with mass
+ * splitting.  Under kind 1 the history value of a contact is the impulse on
+ * its owner over the step (3 doubles) and the rolling impulse (3 doubles),
+ * the last-step forces are impulses / dt, and dt is the implicit step.
+ * Returns -3 for kind 1 when a body has a dynamic z, -1 for a bad kind or
+ * n_iter < 1. */
+int orc_set_stepper(orc_bed* b, int32_t kind, int32_t n_iter);
 
 /* Contact set at the current state (does not step).  method 0 = O(N^2)
  * brute force, 1 = uniform grid.  Pairs (owner sid, partner code) sorted
@@ -110,7 +120,8 @@ int orc_last_reaction(const orc_bed* b, int32_t body, double out6[6]);
  * x,y,z; the plate-sinkage objective is component 2); grad = dJ/d(s_k, mu_t,
  * mu_r), with mu_t and mu_r those of the bed (walls whose mu is negative
  * follow the bed).  The bed state advances as in orc_step.  Returns -3 when
- * a body has a dynamic z (derivatives through it are not provided). */
+ * a body has a dynamic z (derivatives through it are not provided) or the
+ * bed uses the implicit stepper. */
 int orc_tangent_window(orc_bed* b, int64_t n_steps, int32_t body, int32_t component, double* J,
                        double grad3[3]);
 

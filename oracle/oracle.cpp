@@ -153,6 +153,8 @@ struct orc_bed {
   std::vector<double> bz, bvz;  // z_free bodies: origin z and v_z
   std::vector<Contact> last_contacts;
   std::vector<double> lastF, lastT, lastR;
+  int stepper = 0;      // 0: explicit compliant step, 1: SPOOK with projected iterations
+  int n_iter = 0;       // projected iterations per SPOOK step
 };
 
 namespace {
@@ -646,6 +648,239 @@ T step_once(orc_bed& b, State<T>& S, int rbody, int comp = 2) {
   return (c == 0) ? R.x : (c == 1) ? R.y : R.z;
 }
 
+// ---------------------------------------------------------------------------
+// Time-implicit stepper (section "Nonsmooth DEM and multibody dynamics"): the
+// SPOOK discretisation of eq:momentum with the contact laws eq:g_n, eq:G_t and
+// eq:G_r, solved by projected block-Jacobi iterations with mass splitting.
+//
+// Step of length h.  Start velocities v0, free velocities v* = v0 + h g; the
+// new velocities are v+ = v* + M^-1 (sum of contact impulses).  A contact
+// between a and b (b may be a wall) has unit normal n (a toward b), overlap
+// delta > 0 and lever arms l_a = r_a - delta/2, l_b = r_b - delta/2; u is the
+// velocity of a relative to b at the contact point and u_n = u . n.
+//   normal:  0 <= -u_n(v+) + S P + C  perp  P >= 0, with
+//            S = 4 / (k_n e_H h^2 (1 + 4 tau/h) delta^(2 e_H - 2)),
+//            C = (u_n(v0) - 4 delta / (e_H h)) / (1 + 4 tau/h), tau = gamma_n.
+//            This is the SPOOK row of the gap -delta^e_H with compliance
+//            e_H / k_n, divided by its Jacobian scale e_H delta^(e_H - 1) so
+//            that the multiplier P is the normal impulse.
+//   tangent: u_t(v+) = 0 while |p_t| < mu_t P; at |p_t| = mu_t P, p_t opposes u_t.
+//   rolling: w_a - w_b = 0 while |p_r| < mu_r r* P; at the bound p_r opposes it.
+// The impulse on a is -P n + p_t at the contact point plus the moment p_r; b
+// receives the opposite.
+//
+// Iteration: every contact, from the velocities of the previous iteration,
+// solves its own rows one after another (normal, tangent, rolling) against
+// its two bodies with masses and inertias divided by their contact counts,
+// then the velocities are rebuilt from v* and all impulses.  Fixed points
+// satisfy the conditions above.  The history of a contact is its impulse on
+// a (-P n + p_t) and p_r, the warm start of the next step.
+
+struct SpC {
+  int64_t a, b;            // b < 0: wall -1-b
+  V3<double> n;
+  double la, lb;
+  double S, C;
+  double mu_t, mrr;        // mu_t and mu_r r*
+  V3<double> uw, ww;       // wall: velocity at the contact point, angular velocity
+  V3<double> pc;           // contact point
+  int body;
+  double P;
+  V3<double> pt, pr;
+};
+
+inline V3<double> rel_vel(const SpC& c, const V3<double>& va, const V3<double>& wa, const V3<double>& vb,
+                          const V3<double>& wb) {
+  const V3<double> ua = add(va, scl(c.la, cross(wa, c.n)));
+  if (c.b < 0) return sub(ua, c.uw);
+  return add(sub(ua, vb), scl(c.lb, cross(wb, c.n)));
+}
+
+void spook_step(orc_bed& b) {
+  State<double>& S = b.st;
+  const double h = b.p.dt;
+  const double t = (double)b.k * h;
+  const std::vector<BodyPose> bp = body_poses(b, t);
+  const std::vector<WallPose> wp = wall_poses(b, bp);
+  std::vector<Contact> cs = detect(b, S.x, wp, b.n <= 4096 ? 0 : 1);
+  const int64_t nc = (int64_t)cs.size();
+  const double eH = b.p.e_H;
+  const double Estar = 1.0 / ((1.0 - b.p.nu * b.p.nu) / b.p.E + (1.0 - b.p.nu * b.p.nu) / b.p.E);
+  const double tau = b.p.gamma_factor * h;
+  const double ups = 1.0 / (1.0 + 4.0 * tau / h);
+  std::vector<int64_t> deg((size_t)b.n, 0);
+  std::vector<SpC> C((size_t)nc);
+  for (int64_t q = 0; q < nc; ++q) {
+    const Contact& ct = cs[q];
+    SpC& c = C[q];
+    const int64_t i = ct.owner;
+    c.a = i;
+    c.b = ct.partner;
+    const double ri = b.r[i];
+    double delta, dstar;
+    if (ct.partner >= 0) {
+      const int64_t j = ct.partner;
+      V3<double> D = sub(S.x[j], S.x[i]);
+      if (b.periodic & 1u) D.x = D.x + image_shift(D.x, b.L[0]);
+      if (b.periodic & 2u) D.y = D.y + image_shift(D.y, b.L[1]);
+      const double dd = norm(D);
+      c.n = (dd > 0.0) ? scl(1.0 / dd, D) : V3<double>{0.0, 0.0, 1.0};
+      delta = (ri + b.r[j]) - dd;
+      dstar = 2.0 * ri * b.r[j] / (ri + b.r[j]);
+      c.la = ri - 0.5 * delta;
+      c.lb = b.r[j] - 0.5 * delta;
+      c.mu_t = S.mu_t;
+      c.mrr = S.mu_r * 0.5 * dstar;
+      c.body = -1;
+      deg[j] += 1;
+    } else {
+      const WallPose& W = wp[-1 - ct.partner];
+      const BodyPose& Pb = bp[W.body];
+      wall_geom<double>(W, S.x[i], ri, &delta, &c.n);
+      dstar = 2.0 * ri;
+      c.la = ri - 0.5 * delta;
+      c.lb = 0.0;
+      c.pc = add(S.x[i], scl(c.la, c.n));
+      const V3<double> Om = {0.0, 0.0, Pb.omega};
+      c.uw = add(Pb.vel, cross(Om, sub(c.pc, Pb.c)));
+      c.ww = Om;
+      c.mu_t = (W.mu_t < 0.0) ? S.mu_t : W.mu_t;
+      c.mrr = ((W.mu_r < 0.0) ? S.mu_r : W.mu_r) * 0.5 * dstar;
+      c.body = W.body;
+    }
+    deg[i] += 1;
+    const double kn = S.s_k * Estar * std::sqrt(dstar) / 3.0;
+    c.S = 4.0 / (kn * eH * h * h * (1.0 + 4.0 * tau / h) * std::pow(delta, 2.0 * eH - 2.0));
+    const V3<double> vb0 = (c.b >= 0) ? S.v[c.b] : V3<double>{0, 0, 0};
+    const V3<double> wb0 = (c.b >= 0) ? S.w[c.b] : V3<double>{0, 0, 0};
+    const double un0 = dot(rel_vel(c, S.v[i], S.w[i], vb0, wb0), c.n);
+    c.C = ups * (un0 - 4.0 * delta / (eH * h));
+    // warm start from the stored impulse, re-expressed in the new frame
+    const Hist hs = lookup_hist(S, i, ct.partner);
+    const V3<double> J = {hs[0], hs[1], hs[2]};
+    const double Jn = dot(J, c.n);
+    c.P = std::max(0.0, -Jn);
+    c.pt = sub(J, scl(Jn, c.n));
+    c.pr = {hs[3], hs[4], hs[5]};
+  }
+  const V3<double> g = {b.p.g[0], b.p.g[1], b.p.g[2]};
+  std::vector<V3<double>> vs((size_t)b.n), V((size_t)b.n), W((size_t)b.n);
+  for (int64_t i = 0; i < b.n; ++i) vs[i] = add(S.v[i], scl(h, g));
+  const V3<double> zero = {0.0, 0.0, 0.0};
+  // velocities from v*, the start spins and the current impulses
+  auto rebuild = [&]() {
+    std::vector<V3<double>> dv((size_t)b.n, zero), dw((size_t)b.n, zero);
+    for (int64_t q = 0; q < nc; ++q) {
+      const SpC& c = C[q];
+      const V3<double> Ja = add(scl(-c.P, c.n), c.pt);
+      dv[c.a] = add(dv[c.a], Ja);
+      dw[c.a] = add(dw[c.a], add(scl(c.la, cross(c.n, c.pt)), c.pr));
+      if (c.b >= 0) {
+        dv[c.b] = sub(dv[c.b], Ja);
+        dw[c.b] = add(dw[c.b], sub(scl(c.lb, cross(c.n, c.pt)), c.pr));
+      }
+    }
+    for (int64_t i = 0; i < b.n; ++i) {
+      V[i] = add(vs[i], scl(1.0 / b.m[i], dv[i]));
+      W[i] = add(S.w[i], scl(1.0 / b.I[i], dw[i]));
+    }
+  };
+  rebuild();
+  for (int it = 0; it < b.n_iter; ++it) {
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < nc; ++q) {
+      SpC& c = C[q];
+      const int64_t i = c.a;
+      V3<double> va = V[i], wa = W[i], vb = zero, wb = c.ww;
+      const double ima = (double)deg[i] / b.m[i], iIa = (double)deg[i] / b.I[i];
+      double imb = 0.0, iIb = 0.0;
+      if (c.b >= 0) {
+        vb = V[c.b];
+        wb = W[c.b];
+        imb = (double)deg[c.b] / b.m[c.b];
+        iIb = (double)deg[c.b] / b.I[c.b];
+      }
+      // normal row
+      const double un = dot(rel_vel(c, va, wa, vb, wb), c.n);
+      const double Pn = std::max(0.0, c.P - (-un + c.S * c.P + c.C) / (ima + imb + c.S));
+      const double dP = Pn - c.P;
+      c.P = Pn;
+      va = sub(va, scl(ima * dP, c.n));
+      vb = add(vb, scl(imb * dP, c.n));
+      // tangent rows, Coulomb disc
+      const V3<double> u = rel_vel(c, va, wa, vb, wb);
+      const V3<double> ut = sub(u, scl(dot(u, c.n), c.n));
+      const double Dt = ima + imb + c.la * c.la * iIa + c.lb * c.lb * iIb;
+      V3<double> pt = sub(c.pt, scl(1.0 / Dt, ut));
+      const double capt = c.mu_t * Pn, lt = norm(pt);
+      if (lt > capt) pt = (lt > 0.0) ? scl(capt / lt, pt) : zero;
+      const V3<double> dpt = sub(pt, c.pt);
+      c.pt = pt;
+      va = add(va, scl(ima, dpt));
+      wa = add(wa, scl(iIa * c.la, cross(c.n, dpt)));
+      vb = sub(vb, scl(imb, dpt));
+      wb = add(wb, scl(iIb * c.lb, cross(c.n, dpt)));
+      // rolling rows, rolling-resistance ball
+      const V3<double> wr = sub(wa, wb);
+      V3<double> pr = sub(c.pr, scl(1.0 / (iIa + iIb), wr));
+      const double capr = c.mrr * Pn, lr = norm(pr);
+      if (lr > capr) pr = (lr > 0.0) ? scl(capr / lr, pr) : zero;
+      c.pr = pr;
+    }
+    rebuild();
+  }
+  // records: contact forces and torques over the step, body reactions
+  const size_t nb = b.bodies.size();
+  b.last_contacts = cs;
+  b.lastF.assign((size_t)(3 * b.n), 0.0);
+  b.lastT.assign((size_t)(3 * b.n), 0.0);
+  b.lastR.assign(6 * nb, 0.0);
+  std::vector<std::vector<int64_t>> nk((size_t)b.n);
+  std::vector<std::vector<Hist>> nv((size_t)b.n);
+  for (int64_t q = 0; q < nc; ++q) {
+    const SpC& c = C[q];
+    const V3<double> Ja = add(scl(-c.P, c.n), c.pt);
+    const V3<double> Fa = scl(1.0 / h, Ja);
+    const V3<double> Ta = scl(1.0 / h, add(scl(c.la, cross(c.n, c.pt)), c.pr));
+    double* F = &b.lastF[3 * c.a];
+    double* T = &b.lastT[3 * c.a];
+    F[0] += Fa.x; F[1] += Fa.y; F[2] += Fa.z;
+    T[0] += Ta.x; T[1] += Ta.y; T[2] += Ta.z;
+    if (c.b >= 0) {
+      const V3<double> Tb = scl(1.0 / h, sub(scl(c.lb, cross(c.n, c.pt)), c.pr));
+      double* Fb = &b.lastF[3 * c.b];
+      double* Tbp = &b.lastT[3 * c.b];
+      Fb[0] -= Fa.x; Fb[1] -= Fa.y; Fb[2] -= Fa.z;
+      Tbp[0] += Tb.x; Tbp[1] += Tb.y; Tbp[2] += Tb.z;
+    } else {
+      const V3<double> Fw = neg(Fa);
+      const V3<double> Tw = sub(cross(sub(c.pc, bp[c.body].c), Fw), scl(1.0 / h, c.pr));
+      double* R = &b.lastR[6 * c.body];
+      R[0] += Fw.x; R[1] += Fw.y; R[2] += Fw.z;
+      R[3] += Tw.x; R[4] += Tw.y; R[5] += Tw.z;
+    }
+    nk[c.a].push_back(cs[q].partner);
+    nv[c.a].push_back({Ja.x, Ja.y, Ja.z, c.pr.x, c.pr.y, c.pr.z});
+  }
+  S.hkey.swap(nk);
+  S.hval.swap(nv);
+  // positions with the new velocities; wrap periodic axes
+  for (int64_t i = 0; i < b.n; ++i) {
+    S.v[i] = V[i];
+    S.w[i] = W[i];
+    S.x[i] = add(S.x[i], scl(h, V[i]));
+    if (b.periodic & 1u) {
+      if (S.x[i].x >= b.L[0]) S.x[i].x -= b.L[0];
+      else if (S.x[i].x < 0.0) S.x[i].x += b.L[0];
+    }
+    if (b.periodic & 2u) {
+      if (S.x[i].y >= b.L[1]) S.x[i].y -= b.L[1];
+      else if (S.x[i].y < 0.0) S.x[i].y += b.L[1];
+    }
+  }
+  b.k += 1;
+}
+
 bool finite3(const double* a, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(a[i])) return false;
@@ -801,7 +1036,22 @@ int orc_set_history(orc_bed* b, int64_t count, const int64_t* keys2, const doubl
 
 int orc_step(orc_bed* b, int64_t n_steps) {
   if (!b || n_steps < 0) return -1;
-  for (int64_t s = 0; s < n_steps; ++s) step_once<double>(*b, b->st, -1);
+  for (int64_t s = 0; s < n_steps; ++s) {
+    if (b->stepper == 1) spook_step(*b);
+    else step_once<double>(*b, b->st, -1);
+  }
+  return 0;
+}
+
+int orc_set_stepper(orc_bed* b, int32_t kind, int32_t n_iter) {
+  if (!b || kind < 0 || kind > 1) return -1;
+  if (kind == 1) {
+    if (n_iter < 1) return -1;
+    for (const orc_body& B : b->bodies)
+      if (B.z_free) return -3;  // dynamic bodies are not part of the implicit solve
+  }
+  b->stepper = kind;
+  b->n_iter = n_iter;
   return 0;
 }
 
@@ -847,6 +1097,7 @@ int orc_tangent_window(orc_bed* b, int64_t n_steps, int32_t body, int32_t compon
   if (component < 0 || component > 5) return -1;
   for (const orc_body& B : b->bodies)
     if (B.z_free) return -3;  // derivative through a dynamic body is not provided
+  if (b->stepper != 0) return -3;  // derivatives of the explicit step only
   State<Dual> S;
   const State<double>& D = b->st;
   S.x.resize(b->n);

@@ -62,7 +62,8 @@ def lib():
                            ("orc_set_history", [vp, i64, vp, vp]), ("orc_step", [vp, i64]),
                            ("orc_contact_set", [vp, i32, vp, i64, vp]), ("orc_last_contacts", [vp, vp, i64, vp]),
                            ("orc_last_forces", [vp, vp, vp]), ("orc_last_reaction", [vp, i32, vp]),
-                           ("orc_tangent_window", [vp, i64, i32, i32, vp, vp])]:
+                           ("orc_tangent_window", [vp, i64, i32, i32, vp, vp]),
+                           ("orc_set_stepper", [vp, i32, i32])]:
             f = getattr(L, name)
             f.restype = ctypes.c_int
             f.argtypes = args
@@ -134,6 +135,12 @@ class OracleBed:
 
     def step(self, n=1):
         self._ok(lib().orc_step(self._h, int(n)), "step")
+
+    def set_stepper(self, kind, n_iter=0):
+        """kind "explicit" (the compliant step) or "spook" (the time-implicit
+        step with n_iter projected iterations); see lpr_oracle.h."""
+        k = {"explicit": 0, "spook": 1}[kind]
+        self._ok(lib().orc_set_stepper(self._h, k, int(n_iter)), "set_stepper")
 
     def state(self):
         pos = np.zeros((self.n, 3)); vel = np.zeros((self.n, 3)); omg = np.zeros((self.n, 3))
