@@ -314,6 +314,37 @@ lpr_status lpr_set_contact_params(lpr_bed* bed, double s_k, double mu_t, double 
 lpr_status lpr_adjoint_window(lpr_bed* bed, int64_t n_steps, int32_t ckpt_every, int32_t body, double* J,
                               double grad[3]);
 
+/* ---- time-implicit step ----------------------------------------------
+ * Section "Nonsmooth DEM and multibody dynamics": the paper steps its
+ * contact laws (eq:g_n, eq:G_t, eq:G_r) with the SPOOK integrator and a
+ * projected iterative solver, which lets the step exceed the contact period.
+ *
+ * lpr_set_stepper selects the stepper of a bed or batch:
+ *   LPR_STEPPER_EXPLICIT (default): the explicit compliant step.
+ *   LPR_STEPPER_SPOOK: one SPOOK step of length params.dt per call step.
+ *     The gap -delta^e_H with compliance e_H / k_n and damping time
+ *     tau = gamma_factor dt gives each contact a normal row on its normal
+ *     impulse P >= 0; the tangential impulse lies in the Coulomb disc
+ *     |p_t| <= mu_t P and the rolling impulse in |p_r| <= mu_r r* P, each
+ *     removing its relative motion inside the bound and opposing it at the
+ *     bound.  The rows are solved by n_iter projected block-Jacobi sweeps
+ *     with mass splitting (every contact solves its own rows against masses
+ *     divided by its bodies' contact counts; velocities are rebuilt from
+ *     all impulses in a fixed order), in FP64; n_iter is the paper's N_it
+ *     (eq:Nit).  Contacts are the pairs overlapping at the start of the
+ *     step.  The history record of a contact is then its impulse on the
+ *     owner over the step (xi_t) and its rolling impulse (xi_r), the warm
+ *     start of the next step; lpr_read_forces gives impulses / dt, and body
+ *     reactions are impulses / dt.
+ *   Returns LPR_E_INVAL for an unknown kind, n_iter outside [1, 100000], a
+ *   bed with candidate lists (rebuild_every > 1 or skin > 0: the implicit
+ *   step searches every step) or a body with a dynamic z.  The first SPOOK
+ *   selection allocates about 2.3 kB per particle (rows and impulses of 16
+ *   owner slots and the walls); lpr_set_contact_params also updates the
+ *   implicit step.  The adjoint window refuses an implicit bed (LPR_E_STATE). */
+enum { LPR_STEPPER_EXPLICIT = 0, LPR_STEPPER_SPOOK = 1 };
+lpr_status lpr_set_stepper(lpr_bed* bed, int32_t kind, int32_t n_iter);
+
 const char* lpr_status_str(lpr_status s);
 /* Message of the last error on the calling thread ("" if none). */
 const char* lpr_last_error(void);

@@ -750,7 +750,9 @@ void spook_step(orc_bed& b) {
     }
     deg[i] += 1;
     const double kn = S.s_k * Estar * std::sqrt(dstar) / 3.0;
-    c.S = 4.0 / (kn * eH * h * h * (1.0 + 4.0 * tau / h) * std::pow(delta, 2.0 * eH - 2.0));
+    // an overlap that rounds to zero has no stiffness: its row cannot push
+    c.S = (delta > 0.0) ? 4.0 / (kn * eH * h * h * (1.0 + 4.0 * tau / h) * std::pow(delta, 2.0 * eH - 2.0))
+                        : 1e300;
     const V3<double> vb0 = (c.b >= 0) ? S.v[c.b] : V3<double>{0, 0, 0};
     const V3<double> wb0 = (c.b >= 0) ? S.w[c.b] : V3<double>{0, 0, 0};
     const double un0 = dot(rel_vel(c, S.v[i], S.w[i], vb0, wb0), c.n);

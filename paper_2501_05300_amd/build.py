@@ -18,7 +18,7 @@ HIP_FLAGS = [
     # keep packed FP32 instructions out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
-HIP_SOURCES = ["lpr_kernels.hip", "lpr_adjoint.hip", "lpr_runtime.hip"]
+HIP_SOURCES = ["lpr_kernels.hip", "lpr_adjoint.hip", "lpr_spook.hip", "lpr_runtime.hip"]
 
 
 def _run(cmd, verbose):

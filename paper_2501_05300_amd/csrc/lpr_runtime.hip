@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "lpr_kernels.h"
+#include "lpr_spook.h"
 #include "lprdem.h"
 
 using namespace lpr;
@@ -143,6 +144,11 @@ struct lpr_bed {
   };
   std::vector<Ckpt> ckpts;
   double* theta_out = nullptr;
+  // time-implicit stepper (allocated on first selection)
+  int stepper = LPR_STEPPER_EXPLICIT;
+  int n_iter = 0;
+  bool sp_ready = false;
+  SpBufs sp{};
 
   void* dalloc(size_t bytes) {
     bytes = (bytes + 255) & ~(size_t)255;
@@ -391,11 +397,30 @@ void enqueue_rebuild(lpr_bed* b) {
   b->rebuilds += 1;
 }
 
+// The contact solve of one step at the current parities (the rebuild, if
+// any, already enqueued): the fused explicit step kernel, or the implicit
+// step's rows, n_iter projected sweeps and finish.  Returns the block size
+// whose reaction partials the body reduction reads.
+int enqueue_contact_step(lpr_bed* b, hipStream_t sm) {
+  if (b->stepper == LPR_STEPPER_SPOOK) {
+    launch_sp_rows(b->d, b->sp, b->s, b->h, b->l, sm);
+    launch_sp_vel(b->d, b->sp, b->s, b->l, 1, sm);
+    for (int it = 0; it < b->n_iter; ++it) {
+      launch_sp_contacts(b->d, b->sp, b->s, b->l, sm);
+      launch_sp_vel(b->d, b->sp, b->s, b->l, 0, sm);
+    }
+    launch_sp_finish(b->d, b->sp, b->s, b->h, b->l, b->record, sm);
+    return SP_BS;
+  }
+  StepPar p{b->s, b->h, b->l, false};
+  launch_step(b->d, p, b->block, b->record, b->persist_blocks, sm);
+  return b->block;
+}
+
 void enqueue_step(lpr_bed* b) {
   if (b->since >= b->R_eff) enqueue_rebuild(b);
-  StepPar p{b->s, b->h, b->l, false};
-  launch_step(b->d, p, b->block, b->record, b->persist_blocks, b->stream);
-  launch_advance(b->d, b->block, b->stream);
+  const int pb = enqueue_contact_step(b, b->stream);
+  launch_advance(b->d, pb, b->stream);
   b->s ^= 1;
   b->h ^= 1;
   b->since += 1;
@@ -773,10 +798,9 @@ lpr_status lpr_step_profiled(lpr_bed* b, int64_t n_steps, double out[4]) {
     HIPTRY(hipEventRecord(ev[4 * q + 0], b->stream));
     if (b->since >= b->R_eff) enqueue_rebuild(b);
     HIPTRY(hipEventRecord(ev[4 * q + 1], b->stream));
-    StepPar p{b->s, b->h, b->l, false};
-    launch_step(b->d, p, b->block, b->record, b->persist_blocks, b->stream);
+    const int pb = enqueue_contact_step(b, b->stream);
     HIPTRY(hipEventRecord(ev[4 * q + 2], b->stream));
-    launch_advance(b->d, b->block, b->stream);
+    launch_advance(b->d, pb, b->stream);
     HIPTRY(hipEventRecord(ev[4 * q + 3], b->stream));
     b->s ^= 1;
     b->h ^= 1;
@@ -1343,6 +1367,66 @@ lpr_status set_device_skin(lpr_bed* b, float skin) {
 
 }  // namespace
 
+static lpr_status upload_sp_consts(lpr_bed* b) {
+  std::vector<SpConst> sc(b->hb.size());
+  for (size_t q = 0; q < b->hb.size(); ++q) {
+    const lpr_params& P = b->hb[q].params;
+    const double Estar = 1.0 / ((1.0 - P.nu * P.nu) / P.E + (1.0 - P.nu * P.nu) / P.E);
+    const double h = P.dt, tau = P.gamma_factor * P.dt;
+    SpConst& c = sc[q];
+    c.rho = P.rho;
+    c.kfac = P.s_k * Estar / 3.0;
+    c.eH = P.e_H;
+    c.h = h;
+    c.ups = 1.0 / (1.0 + 4.0 * tau / h);
+    c.mu_t = P.mu_t;
+    c.mu_r = P.mu_r;
+    for (int a = 0; a < 3; ++a) c.g[a] = P.g[a];
+  }
+  HIPTRY(hipMemcpy(b->sp.sc, sc.data(), sizeof(SpConst) * sc.size(), hipMemcpyHostToDevice));
+  return LPR_OK;
+}
+
+lpr_status lpr_set_stepper(lpr_bed* b, int32_t kind, int32_t n_iter) {
+  lpr_status g = guard(b);
+  if (g != LPR_OK) return g;
+  if (kind != LPR_STEPPER_EXPLICIT && kind != LPR_STEPPER_SPOOK) return fail(LPR_E_INVAL, "unknown stepper");
+  if (kind == LPR_STEPPER_SPOOK) {
+    if (n_iter < 1 || n_iter > 100000) return fail(LPR_E_INVAL, "n_iter must be in [1, 100000]");
+    if (b->R != 1 || b->skin > 0.f)
+      return fail(LPR_E_INVAL, "the implicit step searches contacts every step (rebuild_every 1, no skin)");
+    for (const HostBed& H : b->hb)
+      for (const lpr_body& B : H.bodies)
+        if (B.z_free) return fail(LPR_E_INVAL, "the implicit step takes prescribed bodies only");
+  }
+  lpr_status st = sync_check(b);
+  if (st != LPR_OK) return st;
+  if (kind == LPR_STEPPER_SPOOK && !b->sp_ready) {
+    const size_t N = (size_t)b->d.N, W = (size_t)b->max_walls;
+    SpBufs& sp = b->sp;
+    bool ok = dal(b, &sp.sc, b->hb.size()) && dal(b, &sp.row, (size_t)K * N) && dal(b, &sp.imp, (size_t)K * N) &&
+              dal(b, &sp.wrow, W * N) && dal(b, &sp.wimp, W * N) && dal(b, &sp.vel, N) && dal(b, &sp.sinv, N) &&
+              dal(b, &sp.flag, N);
+    if (!ok) return fail(LPR_E_NOMEM, "implicit step buffers");
+    sp.nwall_max = b->max_walls;
+    HIPTRY(hipMemset(sp.flag, 0, sizeof(uint32_t) * N));
+    b->sp_ready = true;
+  }
+  if (kind == LPR_STEPPER_SPOOK) {
+    lpr_status cs = upload_sp_consts(b);
+    if (cs != LPR_OK) return cs;
+  }
+  // the captured cycle holds the previous stepper's kernels
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->has_graph = false;
+  b->stepper = kind;
+  b->n_iter = (kind == LPR_STEPPER_SPOOK) ? n_iter : 0;
+  return LPR_OK;
+}
+
 lpr_status lpr_set_contact_params(lpr_bed* b, double s_k, double mu_t, double mu_r) {
   lpr_status g = guard(b);
   if (g != LPR_OK) return g;
@@ -1363,6 +1447,7 @@ lpr_status lpr_set_contact_params(lpr_bed* b, double s_k, double mu_t, double mu
     C.mu_r = (float)P.mu_r;
     HIPTRY(hipMemcpy(b->d.beds + q, &C, sizeof(BedConst), hipMemcpyHostToDevice));
   }
+  if (b->sp_ready) return upload_sp_consts(b);
   return LPR_OK;
 }
 
@@ -1371,6 +1456,8 @@ lpr_status lpr_adjoint_window(lpr_bed* b, int64_t n_steps, int32_t ckpt_every, i
   lpr_status g = guard(b);
   if (g != LPR_OK) return g;
   if (b->hb.size() != 1) return fail(LPR_E_INVAL, "the adjoint window runs on a single bed");
+  if (b->stepper != LPR_STEPPER_EXPLICIT)
+    return fail(LPR_E_STATE, "the adjoint window differentiates the explicit step only");
   const HostBed& H = b->hb[0];
   if (n_steps <= 0 || ckpt_every <= 0 || !J_out || !grad_out) return fail(LPR_E_INVAL, "bad arguments");
   if (body < 0 || body >= H.nbody) return fail(LPR_E_INVAL, "body out of range");

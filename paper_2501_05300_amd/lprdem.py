@@ -28,7 +28,7 @@ _PER_BED = ("get_state", "set_state", "get_history", "set_history", "read_contac
             "reaction_window", "read_body", "set_clock", "get_clock", "set_body_state")
 SYMBOLS = ("lpr_bed_create", "lpr_bed_destroy", "lpr_step", "lpr_step_profiled", "lpr_sync", "lpr_get_stats",
            "lpr_status_str", "lpr_last_error", "lpr_batch_create", "lpr_batch_size", "lpr_set_launch",
-           "lpr_autotune", "lpr_set_contact_params", "lpr_adjoint_window") + tuple("lpr_" + f for f in _PER_BED) + tuple("lpr_batch_" + f for f in _PER_BED)
+           "lpr_autotune", "lpr_set_contact_params", "lpr_adjoint_window", "lpr_set_stepper") + tuple("lpr_" + f for f in _PER_BED) + tuple("lpr_batch_" + f for f in _PER_BED)
 
 
 class LprError(RuntimeError):
@@ -90,6 +90,11 @@ class _History(ctypes.Structure):
                 ("xi_r", ctypes.c_float * 3)]
 
 
+# numpy view of lpr_history (the struct above): 40 bytes, no padding
+_HISTORY_DT = np.dtype([("o", "<i8"), ("p", "<i8"), ("v", "<f4", (6,))])
+assert _HISTORY_DT.itemsize == ctypes.sizeof(_History)
+
+
 class _Tuning(ctypes.Structure):
     _fields_ = [("band_ratio", ctypes.c_float), ("cell_factor", ctypes.c_float), ("block", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
@@ -135,6 +140,7 @@ def load_library(path: str = LIB_PATH):
     sig["lpr_batch_size"] = [vp, ctypes.POINTER(i32)]
     sig["lpr_set_launch"] = [vp, i32, i32]
     sig["lpr_set_contact_params"] = [vp, d, d, d]
+    sig["lpr_set_stepper"] = [vp, i32, i32]
     sig["lpr_adjoint_window"] = [vp, i64, i32, i32, ctypes.POINTER(d), vp]
     sig["lpr_autotune"] = [ctypes.POINTER(ctypes.POINTER(_Desc)), i32, ctypes.POINTER(_Allocator), vp, i32,
                            ctypes.POINTER(_Tuning), ctypes.POINTER(_Tuning), i32, ctypes.POINTER(i32)]
@@ -289,6 +295,13 @@ class _Stepper:
     def set_launch(self, block, persistent=False):
         _check(_lib.lpr_set_launch(self._h, int(block), 1 if persistent else 0), "lpr_set_launch")
 
+    def set_stepper(self, kind, n_iter=0):
+        """kind "explicit" (the compliant step, default) or "spook" (the
+        time-implicit step with n_iter projected iterations per step); see
+        lpr_set_stepper in include/lprdem.h."""
+        k = {"explicit": 0, "spook": 1}[kind]
+        _check(_lib.lpr_set_stepper(self._h, k, int(n_iter)), "lpr_set_stepper")
+
     def set_contact_params(self, s_k, mu_t, mu_r):
         _check(_lib.lpr_set_contact_params(self._h, float(s_k), float(mu_t), float(mu_r)), "lpr_set_contact_params")
 
@@ -327,22 +340,18 @@ class _Stepper:
             self._call("get_history", bed, None, 0, ctypes.byref(tot))
         except CapacityError:
             pass
-        buf = (_History * max(1, tot.value))()
-        self._call("get_history", bed, ctypes.addressof(buf), tot.value, ctypes.byref(tot))
-        arr = np.frombuffer(buf, dtype=np.dtype([("o", "<i8"), ("p", "<i8"), ("v", "<f4", (6,))]),
-                            count=tot.value)
+        arr = np.zeros(max(1, tot.value), _HISTORY_DT)
+        self._call("get_history", bed, arr.ctypes.data, tot.value, ctypes.byref(tot))
+        arr = arr[:tot.value]
         return np.stack([arr["o"], arr["p"]], 1), arr["v"].copy()
 
     def set_history(self, keys, vals, bed=0):
         keys = np.asarray(keys, np.int64).reshape(-1, 2)
         vals = np.asarray(vals, np.float32).reshape(-1, 6)
-        buf = (_History * max(1, len(keys)))()
-        for q in range(len(keys)):
-            buf[q].owner, buf[q].partner = int(keys[q, 0]), int(keys[q, 1])
-            for a in range(3):
-                buf[q].xi_t[a] = float(vals[q, a])
-                buf[q].xi_r[a] = float(vals[q, 3 + a])
-        self._call("set_history", bed, ctypes.addressof(buf), len(keys))
+        arr = np.zeros(max(1, len(keys)), _HISTORY_DT)
+        arr["o"][:len(keys)], arr["p"][:len(keys)] = keys[:, 0], keys[:, 1]
+        arr["v"][:len(keys)] = vals
+        self._call("set_history", bed, arr.ctypes.data, len(keys))
 
     # results of the last step
     def contacts(self, bed=0):

@@ -1,0 +1,176 @@
+"""Time-implicit (SPOOK) step on the GPU against the oracle's FP64 step.
+
+Both sides run the same projected block-Jacobi iteration from the same
+state, history and clock; they differ by summation order and by the GPU
+storing velocities and impulses in FP32 between steps, so one step agrees to
+about 1e-7 relative."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2501_05300_amd import beds
+from parity_util import masses, oracle_from_gpu, oracle_pairs, rel_norm
+
+pytestmark = pytest.mark.gpu
+
+H = 1e-4  # the paper's implicit step (0.10 ms in its bed tables)
+
+
+_SETTLED = {}
+
+
+def raw_spec(seed=0, speed=0.05):
+    """Two-layer bed (2,000 spheres, raft-deposited) under a full-width plate
+    pushed down at `speed`, stepped at 0.1 ms."""
+    spec = beds.two_layer_bed(seed)
+    spec.params = spec.params.replace(dt=H)
+    return beds.add_plate(spec, speed=speed, full_width=True)
+
+
+def implicit_spec(seed=0, speed=0.1):
+    """The two-layer bed settled by 1,500 implicit steps (0.15 s) without a
+    plate, then a full-width plate starting on its highest sphere and pushed
+    down at `speed`."""
+    from paper_2501_05300_amd.lprdem import Bed
+    if seed not in _SETTLED:
+        spec = beds.two_layer_bed(seed)
+        spec.params = spec.params.replace(dt=H)
+        bed = Bed(spec)
+        bed.set_stepper("spook", 40)
+        bed.step(1500)
+        bed.sync()
+        _SETTLED[seed] = bed.state()
+        bed.close()
+    spec = beds.two_layer_bed(seed)
+    spec.params = spec.params.replace(dt=H)
+    x, v, w = _SETTLED[seed]
+    spec.pos, spec.vel, spec.omega = x.copy(), v.copy(), w.copy()
+    return beds.add_plate(spec, speed=speed, full_width=True)
+
+
+def gpu_bed(spec, n_iter, pre=0, **kw):
+    from paper_2501_05300_amd.lprdem import Bed
+    bed = Bed(spec, record_forces=True, **kw)
+    bed.set_stepper("spook", n_iter)
+    if pre:
+        bed.step(pre)
+        bed.sync()
+    return bed
+
+
+def oracle_copy(spec, bed, n_iter):
+    ob = oracle_from_gpu(spec, bed)
+    ob.set_stepper("spook", n_iter)
+    return ob
+
+
+def hist_dict(keys, vals):
+    return {(int(k[0]), int(k[1])): np.asarray(v, np.float64) for k, v in zip(keys, vals)}
+
+
+@pytest.mark.parametrize("n_iter", [1, 40])
+def test_one_step_matches_oracle(n_iter):
+    spec = implicit_spec(speed=0.5)
+    bed = gpu_bed(spec, n_iter, pre=30)
+    ob = oracle_copy(spec, bed, n_iter)
+    x0 = bed.state()[0]
+    bed.step(1)
+    ob.step(1)
+    got, ref = bed.contacts(), oracle_pairs(ob.last_contacts())
+    print("contacts", len(ref), "walls", int(np.sum(ref[:, 1] < 0)))
+    assert len(ref) > 2000 and np.array_equal(got, ref)
+    xg, vg, wg = bed.state()
+    xo, vo, wo = ob.state()
+    assert np.abs(xg - xo).max() < 1e-12
+    assert np.abs(xg - x0).max() > 0
+    assert rel_norm(vg, vo) < 1e-6, rel_norm(vg, vo)
+    assert rel_norm(wg, wo) < 1e-6, rel_norm(wg, wo)
+    F, T = bed.forces()
+    Fo, To = ob.last_forces()
+    assert rel_norm(F, Fo) < 1e-6 and rel_norm(T, To) < 1e-6, (rel_norm(F, Fo), rel_norm(T, To))
+    for q in range(len(spec.bodies)):
+        Rg, Ro = bed.reaction(q), ob.last_reaction(q)
+        assert abs(Ro[2]) > 0
+        assert np.linalg.norm(Rg[:3] - Ro[:3]) < 1e-6 * np.linalg.norm(Ro[:3])
+    hg, ho = hist_dict(*bed.history()), hist_dict(*ob.history())
+    assert set(hg) == set(ho)
+    ks = sorted(ho)
+    a = np.array([hg[k] for k in ks])
+    b = np.array([ho[k] for k in ks])
+    assert rel_norm(a, b) < 1e-6
+
+
+def test_trajectory_stays_with_oracle():
+    """30 steps of a plate pushing into the bed at 0.5 m/s.  The GPU rounds
+    velocities and impulses to FP32 between steps and the oracle does not;
+    the difference grows to about 8e-5 r_min in position and 7e-5 in
+    velocity (measured), bounded here at 5e-4."""
+    spec = implicit_spec(seed=1, speed=0.5)
+    bed = gpu_bed(spec, 30, pre=30)
+    ob = oracle_copy(spec, bed, 30)
+    bed.step(30)
+    ob.step(30)
+    xg, vg, _ = bed.state()
+    xo, vo, _ = ob.state()
+    rmin = float(spec.radius.min())
+    print("max dx / r_min", np.abs(xg - xo).max() / rmin, "v rel", rel_norm(vg, vo))
+    assert np.abs(xg - xo).max() < 5e-4 * rmin
+    assert rel_norm(vg, vo) < 5e-4
+    Rg, Ro = bed.reaction(1), ob.last_reaction(1)
+    assert abs(Ro[2]) > 0 and abs(Rg[2] - Ro[2]) < 5e-4 * abs(Ro[2])
+
+
+def test_static_columns_are_a_fixed_point_on_the_gpu():
+    """Spheres at the Hertz equilibrium and at rest: every contact carries
+    the weight above it and nothing moves (closed form)."""
+    from test_oracle_pins import static_columns
+    spec = static_columns(params=beds.Params(rho=2600.0, dt=H))
+    bed = gpu_bed(spec, 3000)
+    bed.step(1)
+    m, _ = masses(spec)
+    F, _ = bed.forces()
+    np.testing.assert_allclose(F[:, 2], m * 9.81, rtol=2e-6)
+    assert abs(bed.reaction(0)[2] + m.sum() * 9.81) < 1e-6 * m.sum() * 9.81
+    _, v, _ = bed.state()
+    assert np.abs(v).max() < 1e-8
+
+
+def test_captured_cycles_equal_plain_steps_and_batches_equal_single_beds():
+    from paper_2501_05300_amd.lprdem import Batch
+    specs = [raw_spec(seed=2), raw_spec(seed=3, speed=0.02)]
+    plain = gpu_bed(specs[0], 20)
+    plain.step(12)              # captured two-step cycles
+    prof = gpu_bed(specs[0], 20)
+    prof.step_profiled(12)      # uncaptured steps
+    for a, b in zip(plain.state(), prof.state()):
+        assert np.array_equal(a, b)
+    batch = Batch(specs, record_forces=True)
+    batch.set_stepper("spook", 20)
+    batch.step(12)
+    single = gpu_bed(specs[1], 20)
+    single.step(12)
+    for q, ref in ((0, plain), (1, single)):
+        for a, b in zip(batch.state(q), ref.state()):
+            assert np.array_equal(a, b)
+        assert np.array_equal(batch.reaction(1, q), ref.reaction(1))
+
+
+def test_refusals():
+    from paper_2501_05300_amd.lprdem import Bed, LprError
+    spec = raw_spec()
+    skin = Bed(spec, rebuild_every=10, skin=0.25 * float(spec.radius.min()))
+    with pytest.raises(LprError):
+        skin.set_stepper("spook", 10)
+    weighted = raw_spec()
+    weighted.bodies[1].z_free = 1          # a plate under dead weight: a dynamic body
+    weighted.bodies[1].mass = 1.0
+    with pytest.raises(LprError):
+        Bed(weighted).set_stepper("spook", 10)
+    bed = gpu_bed(spec, 10)
+    with pytest.raises(LprError):
+        bed.set_stepper("spook", 0)
+    with pytest.raises(LprError):
+        bed.adjoint_window(10, 5, 1)
+    bed.set_stepper("explicit")   # back to the explicit step (too stiff to step at this dt)
+    bed.sync()
