@@ -269,6 +269,50 @@ def calibration_leg(n, window, ckpt, settle, seed=0):
             "s_per_evaluation": t_fit / max(evals, 1)}
 
 
+def implicit_leg(spec, steps, warmup, n_iter):
+    """The paper's time-implicit step (SPOOK with projected block-Jacobi
+    sweeps) on the settled bed `spec` at the paper's dt = 0.1 ms with n_iter
+    sweeps per step (its refined beds use 215-275, table
+    tab:bed-configurations-refinement): particle-steps/s, simulated time per
+    wall time against the explicit step's, and the sweep kernels' rate
+    against HBM bandwidth."""
+    import torch
+    from paper_2501_05300_amd.lprdem import Bed
+    s = spec.copy()
+    s.params = s.params.replace(dt=1e-4)
+    bed = Bed(s)
+    bed.set_stepper("spook", n_iter)
+    bed.step(warmup)
+    bed.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prof = bed.step_profiled(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = bed.stats()
+    bed.close()
+    N = s.n
+    c_bar = st["contacts"] / N
+    solve_ms = prof["step"] / steps
+    sweep_ms = solve_ms / (n_iter + 1)      # n_iter sweeps plus rows, first velocities and finish
+    # bytes one sweep must move (contacts kernel + velocity kernel): per
+    # particle its velocity iterate (64 B read, 64 B written), split inverse
+    # masses (16), flags (4 + 4), state (64) and list offsets (8); per contact
+    # its rows (64) and impulses (64 read, 64 written) in the contacts kernel,
+    # rows and impulses again (128) in the velocity kernel, partner index and
+    # reverse entry (8)
+    b_sweep = 224.0 + 332.0 * c_bar
+    log(f"implicit: {steps} steps x {n_iter} sweeps in {wall:.3f} s ({1e3 * wall / steps:.2f} ms/step); "
+        f"contacts/particle {c_bar:.3f}; {prof}")
+    return {"dt_s": 1e-4, "sweeps_per_step": n_iter, "steps": steps, "n": N,
+            "ms_per_step": 1e3 * wall / steps, "particle_steps_per_s": N * steps / wall,
+            "simulated_s_per_wall_s": 1e-4 * steps / wall,
+            "contact_sweeps_per_s": st["contacts"] * n_iter * steps / (prof["step"] / 1e3),
+            "kernel_ms_per_step": {k: v / steps for k, v in prof.items()},
+            "algorithmic_bytes_per_particle_sweep": b_sweep,
+            "sweep_hbm_frac": N * b_sweep / (sweep_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+
+
 def configs_leg(steps_c2, steps_c3, warmup, settle):
     """The survey's other workloads on the plain stepper (every-step search):
     a 200k graded bed under a 0.1 m plate pushed at 0.01 m/s, and the
@@ -354,6 +398,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=300, help="timed steps of the 36-bed leg (0: skip)")
     ap.add_argument("--batch-settle", type=int, default=40000)
     ap.add_argument("--adjoint-window", type=int, default=2000, help="steps of the adjoint leg (0: skip)")
+    ap.add_argument("--implicit-steps", type=int, default=10,
+                    help="timed steps of the time-implicit leg on the same bed (0: skip)")
+    ap.add_argument("--implicit-sweeps", type=int, default=250)
     ap.add_argument("--calibrate-window", type=int, default=2000,
                     help="steps per experiment of the calibration leg (0: skip)")
     ap.add_argument("--configs", action="store_true",
@@ -472,6 +519,9 @@ def main():
         out["cpu_baseline"] = cpu_baseline(spec, pos, vel.astype(np.float64), omg.astype(np.float64), keys,
                                            vals.astype(np.float64), clock, args.cpu_steps)
     bed.close()
+    if args.implicit_steps > 0:
+        out["implicit"] = implicit_leg(spec, args.implicit_steps, 4, args.implicit_sweeps)
+        out["implicit"]["explicit_simulated_s_per_wall_s"] = spec.params.dt * args.steps / wall
     if args.batch_steps > 0:
         out["batched"] = batch_leg(args.batch_steps, 100, args.batch_settle, 10)
     if args.adjoint_window > 0:

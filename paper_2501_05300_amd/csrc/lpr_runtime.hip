@@ -406,7 +406,7 @@ int enqueue_contact_step(lpr_bed* b, hipStream_t sm) {
     launch_sp_rows(b->d, b->sp, b->s, b->h, b->l, sm);
     launch_sp_vel(b->d, b->sp, b->s, b->l, 1, sm);
     for (int it = 0; it < b->n_iter; ++it) {
-      launch_sp_contacts(b->d, b->sp, b->s, b->l, sm);
+      launch_sp_contacts(b->d, b->sp, b->l, sm);
       launch_sp_vel(b->d, b->sp, b->s, b->l, 0, sm);
     }
     launch_sp_finish(b->d, b->sp, b->s, b->h, b->l, b->record, sm);
@@ -1406,7 +1406,7 @@ lpr_status lpr_set_stepper(lpr_bed* b, int32_t kind, int32_t n_iter) {
     SpBufs& sp = b->sp;
     bool ok = dal(b, &sp.sc, b->hb.size()) && dal(b, &sp.row, (size_t)K * N) && dal(b, &sp.imp, (size_t)K * N) &&
               dal(b, &sp.wrow, W * N) && dal(b, &sp.wimp, W * N) && dal(b, &sp.vel, N) && dal(b, &sp.sinv, N) &&
-              dal(b, &sp.flag, N);
+              dal(b, &sp.flag, N) && dal(b, &sp.own, N) && dal(b, &sp.cb, (size_t)K * N);
     if (!ok) return fail(LPR_E_NOMEM, "implicit step buffers");
     sp.nwall_max = b->max_walls;
     HIPTRY(hipMemset(sp.flag, 0, sizeof(uint32_t) * N));

@@ -49,9 +49,17 @@ struct SpImp {
   double rx, ry, rz, pad;
 };
 
-// Velocity iterate of one particle (w components unused).
+// Velocity iterate of one particle with its split inverse mass and inertia
+// (contact count / m, contact count / I): one 64-byte read per partner.
 struct SpVel {
-  double4 v, w;
+  double vx, vy, vz, ima;
+  double wx, wy, wz, iIa;
+};
+
+// Sum of impulses (force part, moment part) on one particle, or the part a
+// contact gives its partner.
+struct SpSum {
+  double fx, fy, fz, tx, ty, tz;
 };
 
 struct SpBufs {
@@ -62,17 +70,21 @@ struct SpBufs {
   SpImp* wimp;      // [nwall_max][N]
   SpVel* vel;       // [N]
   double2* sinv;    // [N] contact count / m, contact count / I (split inverse mass and inertia)
+  SpSum* own;       // [N] impulses of a particle's owner-side contacts (slots and walls), one sweep
+  SpSum* cb;        // [K][N] what each owner slot's contact gives its partner, one sweep (zero out of contact)
   uint32_t* flag;   // [N] owner slots (bits 0-15) and walls (bits 16-31) in contact
   int32_t nwall_max;
 };
 
 // Rows and warm starts of every contact at state s; reads history parity h.
 void launch_sp_rows(const DevBufs& d, const SpBufs& sp, int s, int h, int l, hipStream_t st);
-// Velocities from the free velocities and all impulses; first = 1 also
-// stores the split inverse masses.
+// Velocities from the free velocities and all impulses.  first = 1 reads
+// the impulses themselves and stores the split inverse masses; later sweeps
+// add the owner-side sums and the partner parts the contacts kernel wrote.
 void launch_sp_vel(const DevBufs& d, const SpBufs& sp, int s, int l, int first, hipStream_t st);
-// One projected block-Jacobi sweep over every contact.
-void launch_sp_contacts(const DevBufs& d, const SpBufs& sp, int s, int l, hipStream_t st);
+// One projected block-Jacobi sweep over every contact; also writes the
+// owner-side sums and the partner parts the next velocity rebuild adds.
+void launch_sp_contacts(const DevBufs& d, const SpBufs& sp, int l, hipStream_t st);
 // New state, history (parity h ^ 1), contact flags, force records and body
 // reaction partials (blocks of SP_BS particles).
 void launch_sp_finish(const DevBufs& d, const SpBufs& sp, int s, int h, int l, int record, hipStream_t st);

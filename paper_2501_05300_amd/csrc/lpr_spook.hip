@@ -22,8 +22,11 @@
 // previous sweep's velocities, against its bodies' masses and inertias
 // divided by their contact counts; the velocities are then rebuilt from v*
 // and every impulse, per particle in a fixed order (owner slots, reverse
-// list, walls).  Fixed points satisfy the rows above; the result does not
-// depend on thread scheduling.
+// list, walls).  To read each contact once per sweep, the contacts kernel
+// also writes every particle's owner-side sum and, per owner slot, the part
+// of the impulse its partner receives; the velocity kernel adds those.
+// Fixed points satisfy the rows above; the result does not depend on thread
+// scheduling.
 #include "lpr_spook.h"
 
 #include <hip/hip_runtime.h>
@@ -43,7 +46,6 @@ __device__ __forceinline__ D3 cross(D3 a, D3 b) {
   return D3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 __device__ __forceinline__ double nrm(D3 a) { return sqrt(dot(a, a)); }
-__device__ __forceinline__ D3 from4(double4 a) { return D3{a.x, a.y, a.z}; }
 __device__ __forceinline__ D3 from4f(float4 a) { return D3{(double)a.x, (double)a.y, (double)a.z}; }
 
 // Launch block -> work block: the blocks the hardware places on one XCD
@@ -109,7 +111,10 @@ __global__ __launch_bounds__(SP_BS) void k_sp_rows(DevBufs d, SpBufs sp, int s, 
     const PState ot = d.st[s][j];
     double dx, dy, dz;
     const double d2 = pair_sep(bc, me.x, ot.x, dx, dy, dz);
-    if (!sphere_touch(d2, me.x.w, ot.x.w)) continue;
+    if (!sphere_touch(d2, me.x.w, ot.x.w)) {
+      sp.cb[q] = SpSum{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // the partner's sweeps add nothing from this slot
+      continue;
+    }
     const double rj = ot.x.w;
     const double dist = sqrt(d2);
     const D3 n = (d2 > 0.0) ? mk(dx / dist, dy / dist, dz / dist) : mk(0.0, 0.0, 1.0);
@@ -231,13 +236,34 @@ __global__ __launch_bounds__(SP_BS) void k_sp_vel(DevBufs d, SpBufs sp, int s, i
   const double r = me.x.w;
   const double m = sphere_mass(c.rho, r), I = 0.4 * m * r * r;
   D3 dv, dw;
-  const int cnt = impulse_sums(d, sp, l, i, sp.flag[i], dv, dw);
+  double2 si;
+  if (first) {
+    const int cnt = impulse_sums(d, sp, l, i, sp.flag[i], dv, dw);
+    si = make_double2((double)cnt / m, (double)cnt / I);
+    sp.sinv[i] = si;
+  } else {
+    si = sp.sinv[i];
+    const SpSum o = sp.own[i];
+    dv = mk(o.fx, o.fy, o.fz);
+    dw = mk(o.tx, o.ty, o.tz);
+    const uint32_t e0 = d.rev_start[i], e1 = d.rev_start[i + 1];
+    for (uint32_t e = e0; e < e1; ++e) {
+      const uint32_t pk = d.rev_ent[e];
+      const SpSum b = sp.cb[(int64_t)(pk & 15u) * N + (pk >> 4)];
+      dv = add(dv, mk(b.fx, b.fy, b.fz));
+      dw = add(dw, mk(b.tx, b.ty, b.tz));
+    }
+  }
   SpVel V;
-  V.v = make_double4((double)me.v.x + c.h * c.g[0] + dv.x / m, (double)me.v.y + c.h * c.g[1] + dv.y / m,
-                     (double)me.v.z + c.h * c.g[2] + dv.z / m, 0.0);
-  V.w = make_double4((double)me.w.x + dw.x / I, (double)me.w.y + dw.y / I, (double)me.w.z + dw.z / I, 0.0);
+  V.vx = (double)me.v.x + c.h * c.g[0] + dv.x / m;
+  V.vy = (double)me.v.y + c.h * c.g[1] + dv.y / m;
+  V.vz = (double)me.v.z + c.h * c.g[2] + dv.z / m;
+  V.wx = (double)me.w.x + dw.x / I;
+  V.wy = (double)me.w.y + dw.y / I;
+  V.wz = (double)me.w.z + dw.z / I;
+  V.ima = si.x;
+  V.iIa = si.y;
   sp.vel[i] = V;
-  if (first) sp.sinv[i] = make_double2((double)cnt / m, (double)cnt / I);
 }
 
 // One contact's rows, solved in turn against split masses (b a sphere when
@@ -274,18 +300,21 @@ __device__ __forceinline__ void solve_block(D3 n, double la, double lb, double S
   o.rx = pr.x; o.ry = pr.y; o.rz = pr.z;
 }
 
-__global__ __launch_bounds__(SP_BS) void k_sp_contacts(DevBufs d, SpBufs sp, int s, int l) {
+__global__ __launch_bounds__(SP_BS) void k_sp_contacts(DevBufs d, SpBufs sp, int l) {
   if (sp_latched(d.err)) return;
   const int64_t N = d.N;
   const int64_t blk = sp_block(blockIdx.x, N / SP_BS);
   if (blk < 0) return;
   const int64_t i = blk * SP_BS + threadIdx.x;
   const uint32_t fl = sp.flag[i];   // 0 for padding
-  if (fl == 0u) return;
+  if (fl == 0u) {
+    sp.own[i] = SpSum{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    return;
+  }
   const SpConst c = sp.sc[d.chunk_bed32[i >> 8]];
   const SpVel Vi = sp.vel[i];
-  const double2 si = sp.sinv[i];
-  const D3 va = from4(Vi.v), wa = from4(Vi.w);
+  const D3 va = mk(Vi.vx, Vi.vy, Vi.vz), wa = mk(Vi.wx, Vi.wy, Vi.wz);
+  D3 fo = mk(0.0, 0.0, 0.0), to = mk(0.0, 0.0, 0.0);
   uint32_t own = fl & 0xffffu;
   while (own) {
     const int k = __builtin_ctz(own);
@@ -293,12 +322,20 @@ __global__ __launch_bounds__(SP_BS) void k_sp_contacts(DevBufs d, SpBufs sp, int
     const int64_t q = (int64_t)k * N + i;
     const int64_t j = d.own_idx[l][q];
     const SpVel Vj = sp.vel[j];
-    const double2 sj = sp.sinv[j];
     const SpRow r = sp.row[q];
     SpImp o = sp.imp[q];
-    solve_block(mk(r.nx, r.ny, r.nz), r.la, r.lb, r.S, r.C, c.mu_t, r.mrr, si.x, si.y, sj.x, sj.y, va, wa,
-                from4(Vj.v), from4(Vj.w), false, o);
+    const D3 n = mk(r.nx, r.ny, r.nz);
+    solve_block(n, r.la, r.lb, r.S, r.C, c.mu_t, r.mrr, Vi.ima, Vi.iIa, Vj.ima, Vj.iIa, va, wa,
+                mk(Vj.vx, Vj.vy, Vj.vz), mk(Vj.wx, Vj.wy, Vj.wz), false, o);
     sp.imp[q] = o;
+    // impulse on the owner -P n + p_t at the contact point, rolling impulse p_r
+    const D3 pt = mk(o.tx, o.ty, o.tz), pr = mk(o.rx, o.ry, o.rz);
+    const D3 J = sub(pt, scl(o.P, n));
+    const D3 npt = cross(n, pt);
+    fo = add(fo, J);
+    to = add(to, add(scl(r.la, npt), pr));
+    const D3 tb = sub(scl(r.lb, npt), pr);
+    sp.cb[q] = SpSum{-J.x, -J.y, -J.z, tb.x, tb.y, tb.z};
   }
   uint32_t wl = fl >> WALL_BIT;
   while (wl) {
@@ -307,10 +344,15 @@ __global__ __launch_bounds__(SP_BS) void k_sp_contacts(DevBufs d, SpBufs sp, int
     const int64_t q = (int64_t)w * N + i;
     const SpWRow r = sp.wrow[q];
     SpImp o = sp.wimp[q];
-    solve_block(mk(r.nx, r.ny, r.nz), r.la, 0.0, r.S, r.C, r.mut, r.mrr, si.x, si.y, 0.0, 0.0, va, wa,
+    const D3 n = mk(r.nx, r.ny, r.nz);
+    solve_block(n, r.la, 0.0, r.S, r.C, r.mut, r.mrr, Vi.ima, Vi.iIa, 0.0, 0.0, va, wa,
                 mk(r.ux, r.uy, r.uz), mk(0.0, 0.0, r.wz), true, o);
     sp.wimp[q] = o;
+    const D3 pt = mk(o.tx, o.ty, o.tz);
+    fo = add(fo, sub(pt, scl(o.P, n)));
+    to = add(to, add(scl(r.la, cross(n, pt)), mk(o.rx, o.ry, o.rz)));
   }
+  sp.own[i] = SpSum{fo.x, fo.y, fo.z, to.x, to.y, to.z};
 }
 
 __device__ __forceinline__ double sp_wave_sum(double v) {
@@ -405,9 +447,9 @@ __global__ __launch_bounds__(SP_BS) void k_sp_finish(DevBufs d, SpBufs sp, int s
   }
   // positions with the new velocities
   const SpVel V = sp.vel[i];
-  double x = me.x.x + c.h * V.v.x;
-  double y = me.x.y + c.h * V.v.y;
-  const double z = me.x.z + c.h * V.v.z;
+  double x = me.x.x + c.h * V.vx;
+  double y = me.x.y + c.h * V.vy;
+  const double z = me.x.z + c.h * V.vz;
   if (bc.periodic & 1u) {
     if (x >= bc.L[0]) x -= bc.L[0];
     else if (x < 0.0) x += bc.L[0];
@@ -416,13 +458,13 @@ __global__ __launch_bounds__(SP_BS) void k_sp_finish(DevBufs d, SpBufs sp, int s
     if (y >= bc.L[1]) y -= bc.L[1];
     else if (y < 0.0) y += bc.L[1];
   }
-  if (!(isfinite(V.v.x) && isfinite(V.v.y) && isfinite(V.v.z) && isfinite(V.w.x) && isfinite(V.w.y) &&
-        isfinite(V.w.z) && isfinite(x) && isfinite(y) && isfinite(z)))
+  if (!(isfinite(V.vx) && isfinite(V.vy) && isfinite(V.vz) && isfinite(V.wx) && isfinite(V.wy) &&
+        isfinite(V.wz) && isfinite(x) && isfinite(y) && isfinite(z)))
     atomicOr(d.err, ERR_NUMERIC);
   PState out;
   out.x = make_double4(x, y, z, me.x.w);
-  out.v = make_float4((float)V.v.x, (float)V.v.y, (float)V.v.z, me.v.w);
-  out.w = make_float4((float)V.w.x, (float)V.w.y, (float)V.w.z, me.w.w);
+  out.v = make_float4((float)V.vx, (float)V.vy, (float)V.vz, me.v.w);
+  out.w = make_float4((float)V.wx, (float)V.wy, (float)V.wz, me.w.w);
   d.st[sn][i] = out;
 }
 
@@ -441,8 +483,8 @@ void launch_sp_vel(const DevBufs& d, const SpBufs& sp, int s, int l, int first, 
   hipLaunchKernelGGL(k_sp_vel, dim3(sp_grid(d)), dim3(SP_BS), 0, st, d, sp, s, l, first);
 }
 
-void launch_sp_contacts(const DevBufs& d, const SpBufs& sp, int s, int l, hipStream_t st) {
-  hipLaunchKernelGGL(k_sp_contacts, dim3(sp_grid(d)), dim3(SP_BS), 0, st, d, sp, s, l);
+void launch_sp_contacts(const DevBufs& d, const SpBufs& sp, int l, hipStream_t st) {
+  hipLaunchKernelGGL(k_sp_contacts, dim3(sp_grid(d)), dim3(SP_BS), 0, st, d, sp, l);
 }
 
 void launch_sp_finish(const DevBufs& d, const SpBufs& sp, int s, int h, int l, int record, hipStream_t st) {

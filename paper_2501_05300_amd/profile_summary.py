@@ -56,7 +56,7 @@ def kernel_source_hash() -> str:
 
 
 def short(name: str) -> str:
-    n = name.split("(")[0].replace("void ", "").replace("lpr::", "")
+    n = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").replace("lpr::", "")
     return n if len(n) <= 27 else n[:24] + "..."
 
 

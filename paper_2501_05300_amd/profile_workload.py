@@ -1,4 +1,5 @@
-"""Profiling workload: the settled 2M-sphere graded bed stepped in one mode,
+"""Profiling workload: the settled 2M-sphere graded bed stepped in one mode
+(every-step search, skin lists, or the time-implicit step),
 plus a plain device copy of known size (the reference for scaling HBM
 counters).  Run it under rocprofv3; the settled state is cached in a file so
 that counter passes need not settle again.
@@ -47,6 +48,8 @@ def main():
     ap.add_argument("--rebuild-every", type=int, default=1)
     ap.add_argument("--skin", type=float, default=0.0)
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--implicit", type=int, default=0,
+                    help="> 0: the time-implicit step at dt 0.1 ms with this many iterations per step")
     args = ap.parse_args()
     import torch
     from paper_2501_05300_amd.lprdem import Bed
@@ -61,7 +64,11 @@ def main():
     torch.cuda.synchronize()
     log(f"copied {args.copy_mib} MiB")
     del a, b
+    if args.implicit > 0:
+        spec.params = spec.params.replace(dt=1e-4)
     bed = Bed(spec, rebuild_every=args.rebuild_every, skin=args.skin)
+    if args.implicit > 0:
+        bed.set_stepper("spook", args.implicit)
     bed.step(max(2 * args.rebuild_every, 4))
     bed.sync()
     t0 = time.perf_counter()
