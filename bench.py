@@ -295,13 +295,15 @@ def implicit_leg(spec, steps, warmup, n_iter):
     c_bar = st["contacts"] / N
     solve_ms = prof["step"] / steps
     sweep_ms = solve_ms / (n_iter + 1)      # n_iter sweeps plus rows, first velocities and finish
-    # bytes one sweep must move (contacts kernel + velocity kernel): per
-    # particle its velocity iterate (64 B read, 64 B written), split inverse
-    # masses (16), flags (4 + 4), state (64) and list offsets (8); per contact
-    # its rows (64) and impulses (64 read, 64 written) in the contacts kernel,
-    # rows and impulses again (128) in the velocity kernel, partner index and
-    # reverse entry (8)
-    b_sweep = 224.0 + 332.0 * c_bar
+    from paper_2501_05300_amd import profile_summary as PS
+    b_sweep = PS.SWEEP_PARTICLE + PS.SWEEP_CONTACT * c_bar   # bytes per particle a sweep must move
+    traffic = None
+    rec_path = os.path.join(PS.PROFILES, "implicit_sweep_counters_metric_bed.json")
+    if os.path.exists(rec_path):
+        with open(rec_path) as f:
+            rec = json.load(f)
+        if rec.get("spook_source_hash") == PS.spook_source_hash() and rec.get("n") == N:
+            traffic = rec["sweep_hbm_bytes"]
     log(f"implicit: {steps} steps x {n_iter} sweeps in {wall:.3f} s ({1e3 * wall / steps:.2f} ms/step); "
         f"contacts/particle {c_bar:.3f}; {prof}")
     return {"dt_s": 1e-4, "sweeps_per_step": n_iter, "steps": steps, "n": N,
@@ -309,8 +311,11 @@ def implicit_leg(spec, steps, warmup, n_iter):
             "simulated_s_per_wall_s": 1e-4 * steps / wall,
             "contact_sweeps_per_s": st["contacts"] * n_iter * steps / (prof["step"] / 1e3),
             "kernel_ms_per_step": {k: v / steps for k, v in prof.items()},
-            "algorithmic_bytes_per_particle_sweep": b_sweep,
-            "sweep_hbm_frac": N * b_sweep / (sweep_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+            "roofline": {"bound": "hbm", "kernels": ["k_sp_contacts", "k_sp_vel"], "unit": "GB/s",
+                         "achieved": N * b_sweep / (sweep_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "frac": N * b_sweep / (sweep_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_particle_sweep": b_sweep, "traffic": traffic,
+                         "traffic_frac": (traffic / (sweep_ms / 1e3) / 1e9 / HBM_PEAK_GBS) if traffic else None}}
 
 
 def configs_leg(steps_c2, steps_c3, warmup, settle):

@@ -55,6 +55,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def spook_source_hash() -> str:
+    """Hash of the implicit step's device code (comments and layout ignored)."""
+    with open(os.path.join(ROOT, "paper_2501_05300_amd", "csrc", "lpr_spook.hip"), encoding="utf-8") as fh:
+        return hashlib.sha256(_code_only(fh.read()).encode()).hexdigest()[:16]
+
+
 def short(name: str) -> str:
     n = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").replace("lpr::", "")
     return n if len(n) <= 27 else n[:24] + "..."
@@ -77,11 +83,11 @@ def counters(d):
     return per
 
 
-def write_trace(src, name, title, args, steps):
+def write_trace(src, name, title, args, steps, step_kernel="k_step"):
     rows = kernel_stats(src)
-    # every step launches the step kernel once, so its calls count the traced
-    # steps (the timed ones and the workload's warm-up)
-    traced = next(c for n, c, a, t, p in rows if n.startswith("k_step"))
+    # every step launches its step (or finish) kernel once, so its calls
+    # count the traced steps (the timed ones and the workload's warm-up)
+    traced = next(c for n, c, a, t, p in rows if n.startswith(step_kernel))
     lines = [f"# rocprofv3 kernel trace: {title}",
              "# commands:",
              f"#   {SETTLE}",
@@ -104,18 +110,18 @@ def scales(fetch, write):
     return COPY_BYTES / big_f, COPY_BYTES / big_w, big_f, big_w
 
 
-def write_traffic(fdir, wdir, avg_us, name, title, args, cbar):
+def write_traffic(fdir, wdir, avg_us, name, title, args, cbar, alg_line=None, steps=6):
     fetch, write = counters(fdir), counters(wdir)
     sf, sw, big_f, big_w = scales(fetch, write)
     lines = [f"# rocprofv3 HBM counters: {title}",
              "# commands:",
              f"#   {SETTLE}",
-             f"#   rocprofv3 --pmc FETCH_SIZE -d <dir> -o run --output-format csv -- {WORK} --steps 6{args}",
-             f"#   rocprofv3 --pmc WRITE_SIZE -d <dir> -o run --output-format csv -- {WORK} --steps 6{args}",
+             f"#   rocprofv3 --pmc FETCH_SIZE -d <dir> -o run --output-format csv -- {WORK} --steps {steps}{args}",
+             f"#   rocprofv3 --pmc WRITE_SIZE -d <dir> -o run --output-format csv -- {WORK} --steps {steps}{args}",
              f"# calibration: a {COPY_BYTES >> 20} MiB device copy reads FETCH_SIZE {big_f / 2**20:.1f} MiB and WRITE_SIZE "
              f"{big_w / 2**20:.1f} MiB, so fetch x{sf:.3f}, write x{sw:.3f}",
-             f"# algorithmic bytes per particle-step B_alg = {B_PARTICLE:.0f} + {B_PAIR:.0f} c (c = {cbar:.3f} pairs per "
-             f"particle) = {B_PARTICLE + B_PAIR * cbar:.1f} B; {N_METRIC} particles",
+             alg_line or (f"# algorithmic bytes per particle-step B_alg = {B_PARTICLE:.0f} + {B_PAIR:.0f} c (c = {cbar:.3f} "
+                          f"pairs per particle) = {B_PARTICLE + B_PAIR * cbar:.1f} B; {N_METRIC} particles"),
              f"{'kernel':<28}{'fetch MB':>10}{'write MB':>10}{'HBM MB':>10}{'avg us':>9}{'GB/s':>9}{'% of 8 TB/s':>12}"]
     rec = {}
     for k in sorted(fetch):
@@ -165,5 +171,50 @@ def main(src, cbar_every=2.42, cbar_skin=2.42):
     print(json.dumps({k: v for k, v in out.items() if k not in ("every_step", "skin_lists")}, indent=1))
 
 
+# Bytes one block-Jacobi sweep of the implicit step must move, per particle
+# and per contact (owner slot or wall).  Contacts kernel: the particle's
+# velocity record (64 B) and flags (4 B) read, its owner-side sum written
+# (48 B); per contact the partner index (4 B), the partner's velocity record
+# (64 B), rows (64 B) and impulses (64 B) read, impulses (64 B) and the
+# partner part (48 B) written.  Velocity kernel: state (64 B), split inverse
+# masses (16 B), owner-side sum (48 B) and list offsets (8 B) read, velocity
+# record (64 B) written; per contact a reverse entry (4 B) and partner part
+# (48 B) read.
+SWEEP_PARTICLE = 64 + 4 + 48 + 64 + 16 + 48 + 8 + 64
+SWEEP_CONTACT = 4 + 64 + 64 + 64 + 64 + 48 + 4 + 48
+
+
+def main_implicit(src, cbar, sweeps=250):
+    """Summaries of the implicit step (dt 0.1 ms, `sweeps` sweeps): kernel
+    trace and HBM counters; returns the sweep kernels' record."""
+    os.makedirs(PROFILES, exist_ok=True)
+    args = f" --implicit {sweeps}"
+    avg, calls = write_trace(os.path.join(src, "trace_implicit"), "kernels_metric_bed_implicit.txt",
+                             f"settled 2,000,000-sphere graded bed, time-implicit step at dt 0.1 ms, {sweeps} sweeps",
+                             args, 6, step_kernel="k_sp_finish")
+    alg = SWEEP_PARTICLE + SWEEP_CONTACT * cbar
+    line = (f"# algorithmic bytes per particle-sweep (contacts + velocity kernels) = {SWEEP_PARTICLE} + "
+            f"{SWEEP_CONTACT} c (c = {cbar:.3f} contacts per particle) = {alg:.1f} B; {N_METRIC} particles")
+    rec, sf, sw = write_traffic(os.path.join(src, "fetch_implicit"), os.path.join(src, "write_implicit"), avg,
+                                "hbm_traffic_metric_bed_implicit.txt",
+                                f"settled 2,000,000-sphere graded bed, time-implicit step, {sweeps} sweeps", args,
+                                cbar, alg_line=line, steps=1)
+    sweep = {k: rec[k] for k in ("k_sp_contacts", "k_sp_vel")}
+    t = sum(r["avg_us"] for r in sweep.values())
+    b = sum(r["fetch_bytes"] + r["write_bytes"] for r in sweep.values())
+    out = {"spook_source_hash": spook_source_hash(), "n": N_METRIC, "sweeps": sweeps, "contacts_per_particle": cbar,
+           "sweep_us": t, "sweep_hbm_bytes": b, "sweep_algorithmic_bytes": alg * N_METRIC,
+           "sweep_counter_frac": b / (t * 1e-6) / 1e9 / 8000.0,
+           "sweep_algorithmic_frac": alg * N_METRIC / (t * 1e-6) / 1e9 / 8000.0, "kernels": sweep}
+    out["source"] = "profiles/hbm_traffic_metric_bed_implicit.txt, profiles/kernels_metric_bed_implicit.txt"
+    with open(os.path.join(PROFILES, "implicit_sweep_counters_metric_bed.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+    return out
+
+
 if __name__ == "__main__":
-    main(sys.argv[1])
+    if len(sys.argv) > 2 and sys.argv[1] == "--implicit":
+        main_implicit(sys.argv[2], float(sys.argv[3]) if len(sys.argv) > 3 else 2.385)
+    else:
+        main(sys.argv[1])
