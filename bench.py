@@ -318,6 +318,24 @@ def implicit_leg(spec, steps, warmup, n_iter):
                          "traffic_frac": (traffic / (sweep_ms / 1e3) / 1e9 / HBM_PEAK_GBS) if traffic else None}}
 
 
+def emission_leg(seed=0):
+    """Layer-by-layer emission of a refined bed shaped like the paper's
+    (d_min 8.5 mm to d_max 30 mm in 6 layers, gamma 0.05, 0.6 m deep, 0.3 m
+    periodic side): wall time, relaxation steps, and the diagnostics the paper
+    reports (bulk density and its local variation, mixing between layers)."""
+    from paper_2501_05300_amd import emission as E
+    d_min, d_max, L, gamma = 8.5e-3, 30e-3, 6, 0.05
+    r = (d_max / d_min) ** (1.0 / L)
+    eta = (r - 1.0) / (r * gamma)
+    bed = E.emit_bed(d_min, r, eta, L, 0.6, 0.3, seed=seed, log=log)
+    dg = E.diagnostics(bed, rho=2200.0)
+    log(f"emission: {dg['n']} spheres in {bed.seconds:.1f} s, {bed.steps} steps; density {dg['density_mean']:.0f} "
+        f"kg/m^3 (rel std {dg['density_rel_std']:.3f}); mixing {[round(m, 4) for m in dg['mixing']]}")
+    return {"d_min": d_min, "d_max": d_max, "ratio": r, "eta": eta, "gamma": E.gamma_of(r, eta), "layers": L,
+            "height_m": 0.6, "side_m": 0.3, "emitted": bed.emitted, "kept": dg["n"], "steps": bed.steps,
+            "seconds": bed.seconds, "diagnostics": dg}
+
+
 def configs_leg(steps_c2, steps_c3, warmup, settle):
     """The survey's other workloads on the plain stepper (every-step search):
     a 200k graded bed under a 0.1 m plate pushed at 0.01 m/s, and the
@@ -408,6 +426,8 @@ def main():
     ap.add_argument("--implicit-sweeps", type=int, default=250)
     ap.add_argument("--calibrate-window", type=int, default=2000,
                     help="steps per experiment of the calibration leg (0: skip)")
+    ap.add_argument("--emission", action="store_true",
+                    help="also build a refined bed layer by layer and report its diagnostics")
     ap.add_argument("--configs", action="store_true",
                     help="also time the plate (200k graded) and grousered-ring (2.0M uniform vs 150k graded) beds")
     ap.add_argument("--settle", type=int, default=40000,
@@ -533,6 +553,8 @@ def main():
         out["adjoint"] = adjoint_leg(50_000, args.adjoint_window, 100, args.settle, 50_000, args.seed)
     if args.calibrate_window > 0:
         out["calibration"] = calibration_leg(50_000, args.calibrate_window, 100, args.settle, args.seed)
+    if args.emission:
+        out["emission"] = emission_leg(args.seed)
     if args.configs:
         out["other_configs"] = configs_leg(20_000, 10_000, 200, args.settle)
     print(json.dumps(out), flush=True)
