@@ -336,6 +336,36 @@ def emission_leg(seed=0):
             "seconds": bed.seconds, "diagnostics": dg}
 
 
+def terramech_leg(seed=0, t_static=0.05, pull_speed=0.5, pull_distance=0.1):
+    """The plate test at one third of the paper's scale: a 0.1 x 0.06 m plate
+    with four 14.3 mm grousers under 16.7 kPa (the paper's 50 kPa scaled
+    with length, as stresses under gravity scale) on 0.2 m deep beds (0.3 x 0.15 m
+    periodic), phase I for t_static, then a pull of pull_distance at
+    pull_speed; a uniform 3 mm reference, a bed refined from 3 to 10 mm
+    (gamma 0.05) and a uniform 10 mm control, with the paper's normalised
+    errors against the reference."""
+    from paper_2501_05300_amd import terramech as T
+    plate = T.Plate()
+    cases = (("uniform_3mm_reference", 3e-3, 3e-3, 0.0), ("refined_3_10mm_gamma_0.05", 3e-3, 10e-3, 0.05),
+             ("uniform_10mm_control", 10e-3, 10e-3, 0.0))
+    out = {}
+    for name, dmin, dmax, gamma in cases:
+        t0 = time.perf_counter()
+        spec = T.linear_bed(dmin, dmax, gamma, 0.2, 0.3, 0.15, seed=seed)
+        t1 = time.perf_counter()
+        res = T.run_protocol(spec, plate, t_static, pull_speed, pull_distance, log=log)
+        t2 = time.perf_counter()
+        out[name] = {"n": spec.n, "prepare_s": t1 - t0, "protocol_s": t2 - t1, "steps": res["steps"],
+                     "particle_steps_per_s": spec.n * res["steps"] / (t2 - t1),
+                     **{k: res[k] for k in ("static_sinkage", "dynamic_sinkage", "peak_traction", "average_traction")}}
+        log(f"{name}: {spec.n} spheres, protocol {t2 - t1:.1f} s")
+    ref = out["uniform_3mm_reference"]
+    for name in list(out):
+        out[name]["errors"] = T.normalized_errors(out[name], ref, plate.h_grouser, plate.load, plate.load)
+        out[name]["count_reduction"] = ref["n"] / out[name]["n"]
+    return out
+
+
 def configs_leg(steps_c2, steps_c3, warmup, settle):
     """The survey's other workloads on the plain stepper (every-step search):
     a 200k graded bed under a 0.1 m plate pushed at 0.01 m/s, and the
@@ -428,6 +458,8 @@ def main():
                     help="steps per experiment of the calibration leg (0: skip)")
     ap.add_argument("--emission", action="store_true",
                     help="also build a refined bed layer by layer and report its diagnostics")
+    ap.add_argument("--terramech", action="store_true",
+                    help="also run the plate test on reference, refined and control beds")
     ap.add_argument("--configs", action="store_true",
                     help="also time the plate (200k graded) and grousered-ring (2.0M uniform vs 150k graded) beds")
     ap.add_argument("--settle", type=int, default=40000,
@@ -555,6 +587,8 @@ def main():
         out["calibration"] = calibration_leg(50_000, args.calibrate_window, 100, args.settle, args.seed)
     if args.emission:
         out["emission"] = emission_leg(args.seed)
+    if args.terramech:
+        out["terramech"] = terramech_leg(args.seed)
     if args.configs:
         out["other_configs"] = configs_leg(20_000, 10_000, 200, args.settle)
     print(json.dumps(out), flush=True)

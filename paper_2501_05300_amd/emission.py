@@ -83,14 +83,16 @@ def emit(rng, layer: Layer, side: float, z_start: float, count: int):
 
 
 def relax(pos, rad, vel, omg, side, params, v_tol=0.02, chunk=4000, max_steps=200_000):
-    """Steps the spheres on the GPU (periodic sides, frictionless floor, the
-    paper's relaxation friction) until the fastest moves slower than v_tol.
-    Returns positions, velocities, spins and the steps taken."""
+    """Steps the spheres on the GPU (periodic sides of length `side`, or
+    (Lx, Ly), frictionless floor, the paper's relaxation friction) until the
+    fastest moves slower than v_tol.  Returns positions, velocities, spins
+    and the steps taken."""
     from .lprdem import Bed
     n = len(rad)
+    Lx, Ly = (side, side) if np.isscalar(side) else side
     spec = beds.BedSpec(pos=np.ascontiguousarray(pos, np.float64), radius=np.asarray(rad, np.float32),
                         vel=np.asarray(vel, np.float32).reshape(n, 3), omega=np.asarray(omg, np.float32).reshape(n, 3),
-                        box=(side, side, 0.0), periodic=3, params=params, walls=[beds.floor_wall(0.0, 0.0)],
+                        box=(Lx, Ly, 0.0), periodic=3, params=params, walls=[beds.floor_wall(0.0, 0.0)],
                         bodies=[beds.Body()], info={"workload": "emission"})
     rmin = float(np.min(rad))
     bed = Bed(spec, rebuild_every=5, skin=0.25 * rmin)

@@ -242,7 +242,10 @@ class _TorchMemory:
         def _release(ctx, p):
             if p in self._live:
                 del self._live[p]
-                torch.cuda.caching_allocator_delete(p)
+                try:
+                    torch.cuda.caching_allocator_delete(p)
+                except (AttributeError, TypeError):
+                    pass  # torch already torn down at interpreter exit; the process frees its memory
 
         self._cb = (_ALLOC(_alloc), _RELEASE(_release))
         self.struct = _Allocator(self._cb[0], self._cb[1], None)
