@@ -338,8 +338,9 @@ def emission_leg(seed=0):
 
 def terramech_leg(seed=0, t_static=0.05, pull_speed=0.5, pull_distance=0.1):
     """The plate test at one third of the paper's scale: a 0.1 x 0.06 m plate
-    with four 14.3 mm grousers under 16.7 kPa (the paper's 50 kPa scaled
-    with length, as stresses under gravity scale) on 0.2 m deep beds (0.3 x 0.15 m
+    with four 14.3 mm grousers under 5 kPa (below this plate's bearing
+    capacity on this sand; the paper's 50 kPa is for a plate three times as
+    large) on 0.2 m deep beds (0.3 x 0.15 m
     periodic), phase I for t_static, then a pull of pull_distance at
     pull_speed; a uniform 3 mm reference, a bed refined from 3 to 10 mm
     (gamma 0.05) and a uniform 10 mm control, with the paper's normalised

@@ -82,11 +82,12 @@ def emit(rng, layer: Layer, side: float, z_start: float, count: int):
     return pos, rad
 
 
-def relax(pos, rad, vel, omg, side, params, v_tol=0.02, chunk=4000, max_steps=200_000):
+def relax(pos, rad, vel, omg, side, params, v_tol=0.02, chunk=4000, max_steps=200_000, min_steps=0):
     """Steps the spheres on the GPU (periodic sides of length `side`, or
-    (Lx, Ly), frictionless floor, the paper's relaxation friction) until the
-    fastest moves slower than v_tol.  Returns positions, velocities, spins
-    and the steps taken."""
+    (Lx, Ly), frictionless floor, the paper's relaxation friction) for at
+    least min_steps and then until the fastest moves slower than v_tol (a
+    packing deposited at rest starts slow: it needs the minimum to compact).
+    Returns positions, velocities, spins and the steps taken."""
     from .lprdem import Bed
     n = len(rad)
     Lx, Ly = (side, side) if np.isscalar(side) else side
@@ -103,7 +104,7 @@ def relax(pos, rad, vel, omg, side, params, v_tol=0.02, chunk=4000, max_steps=20
             bed.sync()
             steps += chunk
             x, v, w = bed.state()
-            if float(np.abs(v).max()) < v_tol:
+            if steps >= min_steps and float(np.abs(v).max()) < v_tol:
                 break
     finally:
         bed.close()

@@ -3,9 +3,10 @@ beds, with the paper's accuracy metric (section "Simulations": the test with
 a grousered plate; section "Results": sinkage, traction and the aggregate
 error).
 
-A rigid plate with grousers below it rests on the bed under a dead weight
-(a body free in z).  Phase I holds it in place horizontally: the sinkage it
-reaches is the static sinkage.  Phases II-III pull it horizontally at a
+A rigid plate with grousers below it is lowered slowly onto the bed until
+the particles carry its load, then left under a dead weight (a body free in
+z).  Phase I holds it in place horizontally: the sinkage it reaches is the
+static sinkage.  Phases II-III pull it horizontally at a
 constant speed while the load stays: the pull force F_T = -R_x (R the
 reaction of the particles on the plate) gives the tractive resistance
 F_T / F_N, its early peak is the initial peak traction, its mean over the
@@ -34,9 +35,10 @@ class Plate:
     h_grouser: float = 0.0143  # grouser depth below the plate face
     t_grouser: float = 0.004   # grouser thickness along x
     t_face: float = 0.005      # plate thickness above the grousers
-    pressure: float = 5.0e4 / 3.0   # normal stress over the plate area (load F_N = pressure * area): the
-                                    # paper's 50 kPa scaled with length (stresses under gravity scale with
-                                    # size; this plate is a third of the paper's)
+    pressure: float = 5.0e3    # normal stress over the plate area (load F_N = pressure * area): below the
+                               # bearing capacity of this plate on this sand (about gamma D N_q + gamma B N_gamma
+                               # / 2, some 9 kPa with the face at grouser depth); the paper's 50 kPa holds
+                               # only for its larger plate
 
     @property
     def load(self) -> float:
@@ -44,17 +46,18 @@ class Plate:
 
 
 def add_grouser_plate(spec: beds.BedSpec, plate: Plate, g: float = 9.81, speed: float = 0.0,
-                      origin_x: float = None, vz0: float = 0.0) -> beds.BedSpec:
+                      origin_x: float = None, vz0: float = 0.0, z_free: bool = True) -> beds.BedSpec:
     """The plate as a body free in z with mass F_N / g (initial vertical
-    speed vz0), grouser tips on the surface under it, moving along x at
-    `speed`: a face box over grouser boxes spanning the width."""
+    speed vz0), or with its vertical motion prescribed at vz0 (z_free
+    False), grouser tips on the surface under it, moving along x at `speed`:
+    a face box over grouser boxes spanning the width."""
     Lx, Ly = spec.box[0], spec.box[1]
     cx, cy = 0.5 * Lx, 0.5 * Ly
     R = 0.5 * math.hypot(plate.length, plate.width)
     z0 = beds.surface_height(spec.pos, spec.radius, cx, cy, R, spec.box) + plate.h_grouser
     b = len(spec.bodies)
     spec.bodies.append(beds.Body(origin=(cx if origin_x is None else origin_x, cy, z0), lin_vel=(speed, 0.0, vz0),
-                                 z_free=1, mass=plate.load / g))
+                                 z_free=1 if z_free else 0, mass=plate.load / g))
     eye = (1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0)
     spec.walls.append(beds.Wall(kind=beds.WALL_BOX, body=b, origin=(0.0, 0.0, 0.5 * plate.t_face), frame=eye,
                                 dims=(0.5 * plate.length, 0.5 * plate.width, 0.5 * plate.t_face)))
@@ -70,8 +73,9 @@ def add_grouser_plate(spec: beds.BedSpec, plate: Plate, g: float = 9.81, speed: 
 def linear_bed(d_min: float, d_max: float, gamma: float, depth: float, Lx: float, Ly: float, seed=0,
                params=None) -> beds.BedSpec:
     """Bed refined by the paper's linear profile d(z) = d_min + gamma z up to
-    d_max (gamma = 0: uniform at d_min), deposited and relaxed with the
-    paper's relaxation friction."""
+    d_max (gamma = 0: uniform at d_min), deposited at rest and relaxed with
+    the paper's relaxation friction for at least 0.3 s, then until it is
+    still."""
     rng = np.random.default_rng(seed)
     prm = params or beds.paper_params()
     prof = beds.linear_profile(d_min, gamma, d_max) if gamma > 0 else (
@@ -80,63 +84,96 @@ def linear_bed(d_min: float, d_max: float, gamma: float, depth: float, Lx: float
     pos, rad = beds.profile_bed(n, prof, depth, Lx, Ly, rng)
     relax_prm = beds.settle_params(prm).replace(dt=5e-6, gamma_factor=10.0)
     z = np.zeros((n, 3), np.float32)
-    pos, _, _, _ = emission.relax(pos, rad, z, z, (Lx, Ly), relax_prm, v_tol=0.02)
+    pos, _, _, _ = emission.relax(pos, rad, z, z, (Lx, Ly), relax_prm, v_tol=0.02,
+                                  min_steps=int(round(0.3 / relax_prm.dt)))
     return beds.BedSpec(pos=pos, radius=rad, vel=np.zeros((n, 3), np.float32), omega=np.zeros((n, 3), np.float32),
                         box=(Lx, Ly, 0.0), periodic=3, params=prm, walls=[beds.floor_wall()], bodies=[beds.Body()],
                         info={"workload": "linear-profile", "d_min": d_min, "d_max": d_max, "gamma": gamma})
 
 
-def run_protocol(spec: beds.BedSpec, plate: Plate, t_static: float, pull_speed: float, pull_distance: float,
-                 samples: int = 60, log=None) -> Dict:
-    """Phase I for t_static seconds, then phases II-III: a pull of
-    pull_distance at pull_speed.  The plate's horizontal motion is
-    prescribed; its height follows the load.  Returns the sinkage and
-    traction series and the four measures."""
+def _phase_bed(spec, plate, state, history, clock, z_start, z, vz, speed, z_free, b_expect):
+    """A bed at (state, history, clock) with the plate at height z (z_start
+    the height its pose is measured from) moving along x at `speed`; its x
+    pose stays where the previous phase left it (x(t) = origin_x + speed t)."""
     from .lprdem import Bed
     dt = spec.params.dt
-    s1 = spec.copy()
-    add_grouser_plate(s1, plate)
-    b = s1.info["plate_body"]
-    z_start = s1.bodies[b].origin[2]
-    bed = Bed(s1)
-    n1 = int(round(t_static / dt))
-    chunk1 = max(1, n1 // samples)
-    t, sink, trac = [], [], []
+    s = spec.copy()
+    s.pos, s.vel, s.omega = state
+    x0 = 0.5 * spec.box[0]
+    if z_free:
+        add_grouser_plate(s, plate, speed=speed, origin_x=x0 - speed * clock * dt)
+        b = s.info["plate_body"]
+        s.bodies[b].origin = (s.bodies[b].origin[0], s.bodies[b].origin[1], z_start)
+    else:  # prescribed descent at vz from z at this clock
+        add_grouser_plate(s, plate, speed=speed, origin_x=x0 - speed * clock * dt, vz0=vz, z_free=False)
+        b = s.info["plate_body"]
+        s.bodies[b].origin = (s.bodies[b].origin[0], s.bodies[b].origin[1], z - vz * clock * dt)
+    assert b == b_expect
+    bed = Bed(s)
+    if history is not None:
+        bed.set_history(*history)
+    bed.set_clock(clock)
+    if z_free:
+        bed.set_body_state(b, z, vz)
+    return bed
+
+
+def run_protocol(spec: beds.BedSpec, plate: Plate, t_static: float, pull_speed: float, pull_distance: float,
+                 samples: int = 60, lower_speed: float = 0.2, log=None) -> Dict:
+    """Lowers the plate at lower_speed until the particles carry its load,
+    then phase I for t_static seconds (free in z under the load, held in x),
+    then phases II-III: a pull of pull_distance at pull_speed.  Returns the
+    sinkage and traction series and the four measures; sinkage is measured
+    from grouser tips resting on the highest sphere under the plate."""
+    dt = spec.params.dt
+    s0 = spec.copy()
+    add_grouser_plate(s0, plate)
+    b = s0.info["plate_body"]
+    z_start = s0.bodies[b].origin[2]
+    state = (spec.pos, spec.vel, spec.omega)
+    # lowering: prescribed descent until the mean reaction over a chunk
+    # reaches the load (at most three grouser depths)
+    bed = _phase_bed(spec, plate, state, None, 0, z_start, z_start, -lower_speed, 0.0, False, b)
+    chunk0 = max(1, int(round(0.05 * plate.h_grouser / lower_speed / dt)))
+    bed.reaction_window(b, reset=True)
     done = 0
-    while done < n1:
-        k = min(chunk1, n1 - done)
-        bed.step(k)
-        done += k
+    while done * dt * lower_speed < 3.0 * plate.h_grouser:
+        bed.step(chunk0)
+        done += chunk0
+        sum6, cnt = bed.reaction_window(b, reset=True)
+        if sum6[2] / max(cnt, 1) >= plate.load:
+            break
+    o, _ = bed.body(b)
+    z_low = float(o[2])
+    state, history, clock = bed.state(), bed.history(), bed.clock()
+    bed.close()
+    if log:
+        log(f"lowering: {done} steps to {(z_start - z_low) * 1e3:.2f} mm")
+    # phase I: free in z under the load
+    bed = _phase_bed(spec, plate, state, history, clock, z_start, z_low, 0.0, 0.0, True, b)
+    n1 = int(round(t_static / dt))
+    bed.step(n1)
     bed.sync()
     o, v = bed.body(b)
     static = z_start - float(o[2])
-    x, vel, w = bed.state()
-    keys, vals = bed.history()
-    clock = bed.clock()
+    state, history, clock = bed.state(), bed.history(), bed.clock()
     bed.close()
     if log:
         log(f"phase I: {n1} steps, static sinkage {static * 1e3:.3f} mm")
-    # phases II-III: the same state with the plate moving along x; its pose
-    # stays continuous (x(t) = origin_x + speed t)
-    s2 = spec.copy()
-    s2.pos, s2.vel, s2.omega = x, vel, w
-    add_grouser_plate(s2, plate, speed=pull_speed, origin_x=0.5 * spec.box[0] - pull_speed * clock * dt)
-    s2.bodies[b].origin = (s2.bodies[b].origin[0], s2.bodies[b].origin[1], z_start)
-    bed = Bed(s2)
-    bed.set_history(keys, vals)
-    bed.set_clock(clock)
-    bed.set_body_state(b, float(o[2]), float(v[2]))
+    # phases II-III: pulled along x under the same load
+    bed = _phase_bed(spec, plate, state, history, clock, z_start, float(o[2]), float(v[2]), pull_speed, True, b)
     n2 = int(round(pull_distance / pull_speed / dt))
     chunk2 = max(1, n2 // samples)
+    t, sink, trac = [], [], []
     bed.reaction_window(b, reset=True)
-    done = 0
-    while done < n2:
-        k = min(chunk2, n2 - done)
+    done2 = 0
+    while done2 < n2:
+        k = min(chunk2, n2 - done2)
         bed.step(k)
-        done += k
+        done2 += k
         sum6, cnt = bed.reaction_window(b, reset=True)
         o2, _ = bed.body(b)
-        t.append(done * dt)
+        t.append(done2 * dt)
         sink.append(z_start - float(o2[2]))
         trac.append(-(sum6[0] / max(cnt, 1)) / plate.load)
     bed.sync()
@@ -145,7 +182,7 @@ def run_protocol(spec: beds.BedSpec, plate: Plate, t_static: float, pull_speed: 
     k_peak = max(1, len(trac) // 3)
     out = {"static_sinkage": static, "dynamic_sinkage": sink[-1], "peak_traction": float(np.max(trac[:k_peak])),
            "average_traction": float(np.mean(trac)), "t": t, "sinkage": sink, "traction": trac.tolist(),
-           "steps": n1 + n2}
+           "steps": done + n1 + n2, "lowering_steps": done}
     if log:
         log(f"phases II-III: {n2} steps, dynamic sinkage {out['dynamic_sinkage'] * 1e3:.2f} mm, peak traction "
             f"{out['peak_traction']:.3f}, average {out['average_traction']:.3f}")
