@@ -368,7 +368,7 @@ def terramech_leg(seed=0, t_static=0.05, pull_speed=0.5, pull_distance=0.1):
 
 
 def configs_leg(steps_c2, steps_c3, warmup, settle):
-    """The survey's other workloads on the plain stepper (every-step search):
+    """Further workloads on the plain stepper (every-step search):
     a 200k graded bed under a 0.1 m plate pushed at 0.01 m/s, and the
     grousered ring (5 kPa dead weight, 0.5 rad/s) on a 2.0M uniform bed and
     on a 150k graded bed (k = 2, L = 0.105 m) in the same 0.4 m box, whose
