@@ -57,3 +57,35 @@ def test_refined_beds_need_fewer_iterations():
     for d_max in (15e-3, 22.5e-3, 30e-3):
         gr = R.iterations(R.contact_network_graded(8.5e-3, d_max, 1.2, 2.0, h), eps)
         assert gr < uni
+
+
+def test_block_jacobi_sweeps_track_the_iteration_rule():
+    """eq:Nit (written for the paper's Gauss-Seidel sweeps) against the
+    oracle's block-Jacobi sweeps: columns of n_d spheres at the Hertz
+    equilibrium, started from zero impulses, reach 1 % error in the floor
+    force within twice N_it = 0.1 n_d / 0.01, and need more sweeps as the
+    column grows."""
+    from oracle import oracle as O
+    from paper_2501_05300_amd import beds
+    from test_oracle_pins import make_spec
+    prm = beds.Params(rho=2600.0, dt=1e-4)
+    Estar = prm.E / (2 * (1 - prm.nu ** 2))
+    r = float(np.float32(1.5e-3))
+    m = prm.rho * 4 / 3 * math.pi * r ** 3
+    needed = []
+    for n in (4, 8, 16):
+        load = m * 9.81 * np.arange(n, 0, -1)
+        z = [r - (load[0] / (Estar * math.sqrt(2 * r) / 3)) ** (2 / 3)]
+        for i in range(1, n):
+            z.append(z[-1] + 2 * r - (load[i] / (Estar * math.sqrt(r) / 3)) ** (2 / 3))
+        spec = make_spec([[0.01, 0.01, zz] for zz in z], [r] * n, params=prm, walls=[beds.floor_wall()],
+                         box=(1, 1, 0))
+        for N in (2 ** k for k in range(13)):
+            b = O.OracleBed(spec)
+            b.set_stepper("spook", N)
+            b.step(1)
+            if abs(-b.last_reaction(0)[2] - load[0]) < 0.01 * load[0]:
+                break
+        needed.append(N)
+        assert N <= 2 * R.iterations(n, 0.01), (n, N)
+    assert needed[0] < needed[1] < needed[2]
