@@ -202,3 +202,18 @@ def test_rotating_grousered_ring_step_matches_oracle():
     assert rel_norm(vg, vo) < 1e-6 and rel_norm(wg, wo) < 1e-6
     Rg, Ro = bed.reaction(b), ob.last_reaction(b)
     assert np.linalg.norm(Rg - Ro) < 1e-6 * np.linalg.norm(Ro)
+
+
+@pytest.mark.parametrize("mu,rolls", [(0.5, True), (0.05, False)])
+def test_incline_closed_forms_on_the_gpu(mu, rolls):
+    """A sphere on a plane tilted by 20 degrees: rolling without slip at
+    (5/7) g sin theta, or sliding at g (sin theta - mu cos theta)."""
+    from test_oracle_spook import incline
+    theta = math.radians(20.0)
+    spec, down = incline(theta, mu)
+    bed = gpu_bed(spec, 20)
+    bed.step(200)
+    v = bed.state()[1][0].astype(np.float64)
+    a = float(v @ down) / (200 * H)
+    ref = (5.0 / 7.0) * 9.81 * math.sin(theta) if rolls else 9.81 * (math.sin(theta) - mu * math.cos(theta))
+    assert abs(a / ref - 1.0) < 1e-3, (a, ref)

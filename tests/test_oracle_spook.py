@@ -253,3 +253,42 @@ def test_fixed_point_does_not_depend_on_the_warm_start():
         few.step(1)
         errs.append(np.abs(few.state()[1] - ref.state()[1]).max())
     assert errs[0] < 0.1 * errs[1]
+
+
+def incline(theta, mu_t, dt=1e-4):
+    """A sphere resting at its static overlap on a plane through the origin
+    tilted by theta about y (its surface descends along +x)."""
+    prm = beds.Params(rho=2600.0, mu_t=mu_t, mu_r=0.0, dt=dt)
+    r = float(np.float32(1.5e-3))
+    m = prm.rho * 4.0 / 3.0 * math.pi * r ** 3
+    kn = prm.E / (2 * (1 - prm.nu ** 2)) * math.sqrt(2 * r) / 3.0
+    nu = np.array([math.sin(theta), 0.0, math.cos(theta)])
+    delta = (m * G * math.cos(theta) / kn) ** (2.0 / 3.0)
+    o = np.array([0.5, 0.5, 0.2])
+    c = o + (r - delta) * nu
+    wall = beds.Wall(kind=beds.WALL_PLANE, body=0, origin=tuple(o), axis=tuple(nu))
+    spec = make_spec([c], [r], params=prm, walls=[wall], box=(1, 1, 0))
+    return spec, np.array([math.cos(theta), 0.0, -math.sin(theta)])
+
+
+def slope_acceleration(b, down, steps, dt):
+    b.step(steps)
+    v = b.state()[1][0]
+    return float(v @ down) / (steps * dt)
+
+
+def test_sphere_rolls_down_an_incline_without_slip():
+    """Enough friction (mu >= (2/7) tan theta): rolling without slip at
+    a = (5/7) g sin theta."""
+    theta = math.radians(20.0)
+    spec, down = incline(theta, 0.5)
+    a = slope_acceleration(spook_bed(spec, 20), down, 200, 1e-4)
+    assert abs(a / ((5.0 / 7.0) * G * math.sin(theta)) - 1.0) < 1e-3
+
+
+def test_sphere_slides_down_an_incline_at_the_coulomb_bound():
+    """Little friction (mu < (2/7) tan theta): sliding at g (sin theta - mu cos theta)."""
+    theta, mu = math.radians(20.0), 0.05
+    spec, down = incline(theta, mu)
+    a = slope_acceleration(spook_bed(spec, 20), down, 200, 1e-4)
+    assert abs(a / (G * (math.sin(theta) - mu * math.cos(theta))) - 1.0) < 1e-3
