@@ -485,3 +485,19 @@ def test_tangent_exact_linear_cases():
         J, g = b.tangent_window(200, 1, comp)
         assert abs(J) > 0
         assert abs(g[q] - J / getattr(prm, mu)) < 1e-9 * abs(J / getattr(prm, mu)), (mu, g, J)
+
+
+@pytest.mark.parametrize("mu,rolls", [(0.5, True), (0.05, False)])
+def test_explicit_step_on_an_incline(mu, rolls):
+    """A sphere on a plane tilted by 20 degrees (a plane wall with a tilted
+    normal): rolling without slip at (5/7) g sin theta, or sliding at
+    g (sin theta - mu cos theta); over 5,000 steps the tangential spring's
+    start-up transient stays below 1e-3 of the acceleration."""
+    from test_oracle_spook import incline
+    theta = math.radians(20.0)
+    spec, down = incline(theta, mu, dt=2e-6)
+    b = O.OracleBed(spec)
+    b.step(5000)
+    a = float(b.state()[1][0] @ down) / (5000 * 2e-6)
+    ref = (5.0 / 7.0) * 9.81 * math.sin(theta) if rolls else 9.81 * (math.sin(theta) - mu * math.cos(theta))
+    assert abs(a / ref - 1.0) < 1e-3
