@@ -84,10 +84,11 @@ def emit(rng, layer: Layer, side: float, z_start: float, count: int):
 
 def relax(pos, rad, vel, omg, side, params, v_tol=0.02, chunk=4000, max_steps=200_000, min_steps=0):
     """Steps the spheres on the GPU (periodic sides of length `side`, or
-    (Lx, Ly), frictionless floor, the paper's relaxation friction) for at
-    least min_steps and then until the fastest moves slower than v_tol (a
-    packing deposited at rest starts slow: it needs the minimum to compact).
-    Returns positions, velocities, spins and the steps taken."""
+    (Lx, Ly), frictionless floor, the paper's relaxation friction) in chunks
+    for at least min_steps and then until the fastest moves slower than
+    v_tol (a packing deposited at rest starts slow: it needs the minimum to
+    compact), at most max_steps (rounded up to whole chunks).  Returns
+    positions, velocities, spins and the steps taken."""
     from .lprdem import Bed
     n = len(rad)
     Lx, Ly = (side, side) if np.isscalar(side) else side
@@ -99,12 +100,12 @@ def relax(pos, rad, vel, omg, side, params, v_tol=0.02, chunk=4000, max_steps=20
     bed = Bed(spec, rebuild_every=5, skin=0.25 * rmin)
     steps = 0
     try:
-        while steps < max_steps:
+        while True:
             bed.step(chunk)
             bed.sync()
             steps += chunk
             x, v, w = bed.state()
-            if steps >= min_steps and float(np.abs(v).max()) < v_tol:
+            if (steps >= min_steps and float(np.abs(v).max()) < v_tol) or steps >= max_steps:
                 break
     finally:
         bed.close()
