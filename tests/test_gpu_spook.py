@@ -217,3 +217,26 @@ def test_incline_closed_forms_on_the_gpu(mu, rolls):
     a = float(v @ down) / (200 * H)
     ref = (5.0 / 7.0) * 9.81 * math.sin(theta) if rolls else 9.81 * (math.sin(theta) - mu * math.cos(theta))
     assert abs(a / ref - 1.0) < 1e-3, (a, ref)
+
+
+def test_contact_parameters_reach_the_implicit_step():
+    """lpr_set_contact_params on an implicit bed: one step with (s_k, mu_t,
+    mu_r) = (2, 0.2, 0.05) against the oracle built with those values."""
+    spec = implicit_spec(speed=0.5)
+    bed = gpu_bed(spec, 30, pre=20)
+    bed.set_contact_params(2.0, 0.2, 0.05)
+    s2 = spec.copy()
+    s2.params = spec.params.replace(s_k=2.0, mu_t=0.2, mu_r=0.05)
+    ob = oracle_copy(s2, bed, 30)
+    ob_default = oracle_copy(spec, bed, 30)     # the bed's own parameters
+    bed.step(1)
+    ob.step(1)
+    ob_default.step(1)
+    assert np.array_equal(bed.contacts(), oracle_pairs(ob.last_contacts()))
+    assert rel_norm(ob_default.state()[1], ob.state()[1]) > 1e-4   # the new parameters change the step
+    _, vg, wg = bed.state()
+    _, vo, wo = ob.state()
+    assert rel_norm(vg, vo) < 1e-6 and rel_norm(wg, wo) < 1e-6
+    F, _ = bed.forces()
+    Fo, _ = ob.last_forces()
+    assert rel_norm(F, Fo) < 1e-6
