@@ -42,3 +42,17 @@ def test_binding_refuses_to_run_without_gpu():
     spec = beds.two_layer_bed(0)
     with pytest.raises(RuntimeError):
         lprdem.Bed(spec)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs one GPU; --gpus above 1 exits with a message before
+    touching a device."""
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode != 0
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
