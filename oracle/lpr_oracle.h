@@ -114,6 +114,14 @@ int orc_contact_set(const orc_bed* b, int32_t method, int64_t* pairs2, int64_t c
 int orc_last_contacts(const orc_bed* b, int64_t* pairs2, int64_t cap, int64_t* n_total);
 int orc_last_forces(const orc_bed* b, double* force3, double* torque3);
 int orc_last_reaction(const orc_bed* b, int32_t body, double out6[6]);
+/* Per contact of the last step, in orc_last_contacts order: the contact
+ * force on the owner (3 doubles each), the rolling-resistance moment on the
+ * owner (3) and the normal force magnitude F_n >= 0 (1).  Under the implicit
+ * stepper these are impulses / dt.  Any pointer may be NULL. */
+int orc_last_contact_loads(const orc_bed* b, double* force3, double* moment3, double* fn);
+/* World pose of wall `wall` at the current clock (the pose the next step
+ * uses): origin (3), normal (3), the three rows of its frame (9). */
+int orc_wall_pose(const orc_bed* b, int32_t wall, double out15[15]);
 
 /* Steps n_steps with forward-mode derivatives.  J = mean over the window of
  * one reaction component on `body` (component 0-2 force x,y,z; 3-5 torque

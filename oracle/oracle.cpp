@@ -153,6 +153,9 @@ struct orc_bed {
   std::vector<double> bz, bvz;  // z_free bodies: origin z and v_z
   std::vector<Contact> last_contacts;
   std::vector<double> lastF, lastT, lastR;
+  // per contact of the last step, in last_contacts order: force on the
+  // owner (3), rolling moment on the owner (3), normal force magnitude
+  std::vector<double> lastCF, lastCM, lastCN;
   int stepper = 0;      // 0: explicit compliant step, 1: SPOOK with projected iterations
   int n_iter = 0;       // projected iterations per SPOOK step
 };
@@ -422,6 +425,7 @@ struct LawOut {
   V3<T> Tj;        // torque on the partner particle (sphere-sphere)
   V3<T> Mr;        // rolling-resistance moment on the owner
   V3<T> p;         // contact point (world, owner's image frame)
+  T Fn;            // normal force magnitude (after the clamp at zero)
   std::array<T, 6> xi;
 };
 
@@ -438,7 +442,7 @@ struct LawIn {
 
 template <class T>
 void contact_law(const orc_params& p, const T& s_k, const LawIn<T>& in, V3<T>* F_out, V3<T>* M_out,
-                 std::array<T, 6>* xi_new) {
+                 std::array<T, 6>* xi_new, T* Fn_out) {
   const double eH = p.e_H;
   const double Estar = 1.0 / ((1.0 - p.nu * p.nu) / p.E + (1.0 - p.nu * p.nu) / p.E);
   const double rstar = 0.5 * in.dstar;
@@ -484,6 +488,7 @@ void contact_law(const orc_params& p, const T& s_k, const LawIn<T>& in, V3<T>* F
   *F_out = add(scl(-Fn, in.n), Ft);
   *M_out = Mr;
   *xi_new = {xt.x, xt.y, xt.z, xr.x, xr.y, xr.z};
+  *Fn_out = Fn;
 }
 
 template <class T>
@@ -526,7 +531,7 @@ LawOut<T> eval_contact(const orc_bed& b, const State<T>& S, const std::vector<Wa
     in.mu_t = S.mu_t;
     in.mu_r = S.mu_r;
     V3<T> F, M;
-    contact_law(b.p, S.s_k, in, &F, &M, &out.xi);
+    contact_law(b.p, S.s_k, in, &F, &M, &out.xi, &out.Fn);
     out.Fi = F;
     out.Mr = M;
     out.Ti = add(cross(ai, F), M);
@@ -552,7 +557,7 @@ LawOut<T> eval_contact(const orc_bed& b, const State<T>& S, const std::vector<Wa
   in.mu_t = (W.mu_t < 0.0) ? S.mu_t : T(W.mu_t);
   in.mu_r = (W.mu_r < 0.0) ? S.mu_r : T(W.mu_r);
   V3<T> F, M;
-  contact_law(b.p, S.s_k, in, &F, &M, &out.xi);
+  contact_law(b.p, S.s_k, in, &F, &M, &out.xi, &out.Fn);
   out.Fi = F;
   out.Mr = M;
   out.Ti = add(cross(ai, F), M);
@@ -611,6 +616,14 @@ T step_once(orc_bed& b, State<T>& S, int rbody, int comp = 2) {
   for (int64_t i = 0; i < b.n; ++i) {
     b.lastF[3 * i + 0] = val(F[i].x); b.lastF[3 * i + 1] = val(F[i].y); b.lastF[3 * i + 2] = val(F[i].z);
     b.lastT[3 * i + 0] = val(Tq[i].x); b.lastT[3 * i + 1] = val(Tq[i].y); b.lastT[3 * i + 2] = val(Tq[i].z);
+  }
+  b.lastCF.assign((size_t)(3 * nc), 0.0);
+  b.lastCM.assign((size_t)(3 * nc), 0.0);
+  b.lastCN.assign((size_t)nc, 0.0);
+  for (int64_t q = 0; q < nc; ++q) {
+    b.lastCF[3 * q + 0] = val(lo[q].Fi.x); b.lastCF[3 * q + 1] = val(lo[q].Fi.y); b.lastCF[3 * q + 2] = val(lo[q].Fi.z);
+    b.lastCM[3 * q + 0] = val(lo[q].Mr.x); b.lastCM[3 * q + 1] = val(lo[q].Mr.y); b.lastCM[3 * q + 2] = val(lo[q].Mr.z);
+    b.lastCN[q] = val(lo[q].Fn);
   }
   b.lastR.assign(6 * nb, 0.0);
   for (size_t q = 0; q < nb; ++q) {
@@ -837,12 +850,18 @@ void spook_step(orc_bed& b) {
   b.lastF.assign((size_t)(3 * b.n), 0.0);
   b.lastT.assign((size_t)(3 * b.n), 0.0);
   b.lastR.assign(6 * nb, 0.0);
+  b.lastCF.assign((size_t)(3 * nc), 0.0);
+  b.lastCM.assign((size_t)(3 * nc), 0.0);
+  b.lastCN.assign((size_t)nc, 0.0);
   std::vector<std::vector<int64_t>> nk((size_t)b.n);
   std::vector<std::vector<Hist>> nv((size_t)b.n);
   for (int64_t q = 0; q < nc; ++q) {
     const SpC& c = C[q];
     const V3<double> Ja = add(scl(-c.P, c.n), c.pt);
     const V3<double> Fa = scl(1.0 / h, Ja);
+    b.lastCF[3 * q + 0] = Fa.x; b.lastCF[3 * q + 1] = Fa.y; b.lastCF[3 * q + 2] = Fa.z;
+    b.lastCM[3 * q + 0] = c.pr.x / h; b.lastCM[3 * q + 1] = c.pr.y / h; b.lastCM[3 * q + 2] = c.pr.z / h;
+    b.lastCN[q] = c.P / h;
     const V3<double> Ta = scl(1.0 / h, add(scl(c.la, cross(c.n, c.pt)), c.pr));
     double* F = &b.lastF[3 * c.a];
     double* T = &b.lastT[3 * c.a];
@@ -1084,6 +1103,29 @@ int orc_last_forces(const orc_bed* b, double* force3, double* torque3) {
   if (!b || b->lastF.size() != (size_t)(3 * b->n)) return -1;
   if (force3) std::memcpy(force3, b->lastF.data(), sizeof(double) * 3 * b->n);
   if (torque3) std::memcpy(torque3, b->lastT.data(), sizeof(double) * 3 * b->n);
+  return 0;
+}
+
+int orc_last_contact_loads(const orc_bed* b, double* force3, double* moment3, double* fn) {
+  if (!b || b->lastCN.size() != b->last_contacts.size()) return -1;
+  const size_t nc = b->last_contacts.size();
+  if (force3 && nc) std::memcpy(force3, b->lastCF.data(), sizeof(double) * 3 * nc);
+  if (moment3 && nc) std::memcpy(moment3, b->lastCM.data(), sizeof(double) * 3 * nc);
+  if (fn && nc) std::memcpy(fn, b->lastCN.data(), sizeof(double) * nc);
+  return 0;
+}
+
+int orc_wall_pose(const orc_bed* b, int32_t wall, double out15[15]) {
+  if (!b || wall < 0 || wall >= (int32_t)b->walls.size()) return -1;
+  const std::vector<BodyPose> bp = body_poses(*b, (double)b->k * b->p.dt);
+  const std::vector<WallPose> wp = wall_poses(*b, bp);
+  const WallPose& W = wp[wall];
+  const V3<double> v[5] = {W.o, W.nu, W.e[0], W.e[1], W.e[2]};
+  for (int q = 0; q < 5; ++q) {
+    out15[3 * q + 0] = v[q].x;
+    out15[3 * q + 1] = v[q].y;
+    out15[3 * q + 2] = v[q].z;
+  }
   return 0;
 }
 

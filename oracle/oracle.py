@@ -63,6 +63,7 @@ def lib():
                            ("orc_contact_set", [vp, i32, vp, i64, vp]), ("orc_last_contacts", [vp, vp, i64, vp]),
                            ("orc_last_forces", [vp, vp, vp]), ("orc_last_reaction", [vp, i32, vp]),
                            ("orc_tangent_window", [vp, i64, i32, i32, vp, vp]),
+                           ("orc_last_contact_loads", [vp, vp, vp, vp]), ("orc_wall_pose", [vp, i32, vp]),
                            ("orc_set_stepper", [vp, i32, i32])]:
             f = getattr(L, name)
             f.restype = ctypes.c_int
@@ -82,7 +83,7 @@ def _ptr(a):
 def _params(p) -> _Params:
     q = _Params()
     for f in ("rho", "E", "nu", "mu_t", "mu_r", "dt", "gamma_factor", "e_H", "kappa_t", "s_k"):
-        setattr(q, f, float(getattr(p, f)))
+        setattr(q, f, p.field(f))
     for a in range(3):
         q.g[a] = float(p.g[a])
     return q
@@ -199,6 +200,20 @@ class OracleBed:
         out = np.zeros(6)
         self._ok(lib().orc_last_reaction(self._h, int(body), _ptr(out)), "last_reaction")
         return out
+
+    def last_contact_loads(self):
+        """Per contact of the last step (last_contacts order): force on the
+        owner (k, 3), rolling moment on the owner (k, 3), F_n (k,)."""
+        k = len(self.last_contacts())
+        F = np.zeros((max(k, 1), 3)); M = np.zeros((max(k, 1), 3)); fn = np.zeros(max(k, 1))
+        self._ok(lib().orc_last_contact_loads(self._h, _ptr(F), _ptr(M), _ptr(fn)), "last_contact_loads")
+        return F[:k], M[:k], fn[:k]
+
+    def wall_pose(self, wall):
+        """World pose of a wall at the current clock: origin, normal, frame (3 x 3 rows)."""
+        out = np.zeros(15)
+        self._ok(lib().orc_wall_pose(self._h, int(wall), _ptr(out)), "wall_pose")
+        return out[0:3], out[3:6], out[6:15].reshape(3, 3)
 
     def tangent_window(self, n_steps, body, component=2):
         """Mean of one reaction component over n_steps and its derivative

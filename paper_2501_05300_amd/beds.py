@@ -57,12 +57,24 @@ class Params:
     dt: float = 2.0e-6           # time step [s]
     gamma_factor: float = 4.5    # gamma_n = gamma_factor * dt
     e_H: float = 1.25            # gap exponent (5/4 Hertz, 1 linear)
-    kappa_t: float = 2 * (1 - 0.15) / (2 - 0.15)  # tangential/normal stiffness ratio
+    kappa_t: Optional[float] = None  # tangential/normal stiffness ratio (None: 2(1-nu)/(2-nu))
     s_k: float = 1.0             # stiffness multiplier
     g: tuple = (0.0, 0.0, -9.81)
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
+
+    def kappa(self) -> float:
+        """The tangential stiffness ratio in effect: the value given, or the
+        Mindlin ratio 2(1 - nu)/(2 - nu) of this parameter set's nu (so a
+        replace(nu=...) moves it along)."""
+        if self.kappa_t is not None:
+            return float(self.kappa_t)
+        return 2.0 * (1.0 - self.nu) / (2.0 - self.nu)
+
+    def field(self, name: str) -> float:
+        """A scalar field for marshalling, with kappa_t resolved."""
+        return self.kappa() if name == "kappa_t" else float(getattr(self, name))
 
 
 def paper_params(**kw) -> Params:

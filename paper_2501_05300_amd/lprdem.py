@@ -170,7 +170,7 @@ def _check(rc, where):
 def params_struct(p) -> _Params:
     q = _Params()
     for f in ("rho", "E", "nu", "mu_t", "mu_r", "dt", "gamma_factor", "e_H", "kappa_t", "s_k"):
-        setattr(q, f, float(getattr(p, f)))
+        setattr(q, f, p.field(f))
     for a in range(3):
         q.g[a] = float(p.g[a])
     return q

@@ -1,0 +1,472 @@
+"""Closed-form pins of the oracle's wall geometry, moving walls, body
+reactions, dead-weight bodies and spring rotation (CPU only).
+
+Each expected value here is computed from geometry or mechanics written out
+in the test (a numerical minimisation over the wall surface, a rigid-body
+rotation, the discrete free-fall sum, the Hertz law k_n delta^(3/2)), not by
+re-running the oracle's own formulas:
+
+  * sphere-wall signed distance for the annulus (face, inner rim, outer rim,
+    back side) and the box (faces, edges, corners, inside) against a bounded
+    minimisation of |x - q|^2 over the wall surface;
+  * the velocity of a spinning wall at the contact point, Omega z x (p - c),
+    through the first-step spring of a held sphere;
+  * the torque on a spinning annulus from a sphere in full Coulomb slip,
+    -mu_t F_n r_c about the axis (section "Nonsmooth DEM and multibody
+    dynamics", eq:G_t; the ring test of section "Pressure-sinkage and
+    shear-displacement");
+  * the reaction force and torque on a body from a known contact force at a
+    known lever arm, including a rolling-resistance moment (eq:momentum,
+    eq:G_r);
+  * a dead-weight body in free fall (the exact semi-implicit Euler sum) and
+    resting on a Hertz column (reaction = its weight);
+  * a stuck tangential spring co-rotating with a rigidly rotating pair (the
+    spring must follow the contact frame, keeping its length).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+from oracle import oracle as O
+from paper_2501_05300_amd import beds
+
+R_SPH = float(np.float32(1.5e-3))
+
+
+def spec_of(pos, rad, vel=None, omg=None, params=None, walls=(), bodies=None, box=(1.0, 1.0, 0.0), periodic=0):
+    n = len(rad)
+    return beds.BedSpec(pos=np.ascontiguousarray(pos, np.float64), radius=np.asarray(rad, np.float32),
+                        vel=np.zeros((n, 3), np.float32) if vel is None else np.asarray(vel, np.float32),
+                        omega=np.zeros((n, 3), np.float32) if omg is None else np.asarray(omg, np.float32),
+                        box=box, periodic=periodic, params=params or beds.Params(g=(0.0, 0.0, 0.0)),
+                        walls=list(walls), bodies=bodies or [beds.Body()])
+
+
+def kn_wall(params, r):
+    """The paper's k_n = E* sqrt(d*) / 3 with d* = 2 r against a wall of the
+    same material."""
+    Estar = params.E / (2.0 * (1.0 - params.nu ** 2))
+    return params.s_k * Estar * math.sqrt(2.0 * r) / 3.0
+
+
+def rot_z(th):
+    c, s = math.cos(th), math.sin(th)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+# ---------------------------------------------------------------------------
+# signed distance: annulus and box against a minimisation over the surface
+
+def annulus_distance(x, o, e0, e1, rin, rout):
+    """min |x - q| over q = o + rho (cos phi e0 + sin phi e1), rho in [rin, rout]."""
+    S = 1e3  # work in millimetres so that the minimiser's tolerances are well scaled
+    rel = (x - o) * S
+    phi0 = math.atan2(rel @ e1, rel @ e0)
+
+    def f(z):
+        u = math.cos(z[1]) * e0 + math.sin(z[1]) * e1
+        du = -math.sin(z[1]) * e0 + math.cos(z[1]) * e1
+        d = rel - z[0] * u
+        return float(d @ d), np.array([-2.0 * (d @ u), -2.0 * z[0] * (d @ du)])
+
+    best = None
+    for rho0 in (rin, 0.5 * (rin + rout), rout):
+        for dphi in (0.0, 0.3, -0.3):
+            r = minimize(f, [rho0 * S, phi0 + dphi], jac=True, method="L-BFGS-B",
+                         bounds=[(rin * S, rout * S), (None, None)],
+                         options={"ftol": 1e-15, "gtol": 1e-13, "maxiter": 1000})
+            if best is None or r.fun < best.fun:
+                best = r
+    z = best.x
+    q = o + (z[0] / S) * (math.cos(z[1]) * e0 + math.sin(z[1]) * e1)
+    return math.sqrt(best.fun) / S, q
+
+
+def box_distance(x, o, axes, half):
+    """Distance from x to the box (0 inside) and the closest surface point,
+    by a bounded minimisation in the box's own coordinates; for a point
+    inside, the depth to the nearest face plane (checked over all six)."""
+    A = np.asarray(axes)
+    l = A @ (x - o)
+    if np.all(np.abs(l) < half):
+        depths = [(half[a] - s * l[a], a, s) for a in range(3) for s in (1.0, -1.0)]
+        d, a, s = min(depths)
+        return -d, x + d * s * A[a]
+
+    S = 1e3  # millimetres
+    rel = (x - o) * S
+
+    def f(y):
+        d = A.T @ y - rel
+        return float(d @ d), 2.0 * (A @ d)
+
+    r = minimize(f, np.clip(l * S, -half * S, half * S) * 0.5, jac=True, method="L-BFGS-B",
+                 bounds=[(-h * S, h * S) for h in half], options={"ftol": 1e-15, "gtol": 1e-13, "maxiter": 1000})
+    return math.sqrt(r.fun) / S, o + A.T @ (r.x / S)
+
+
+def one_step_wall_loads(pos, r, walls, bodies):
+    """One step of held spheres (zero velocity, no gravity, no history), so
+    every wall force is the elastic Hertz force -k_n delta^(3/2) n.  Returns
+    the wall-contact force of each sphere in contact with the wall (spheres
+    may also touch each other; those forces are left out)."""
+    prm = beds.Params(g=(0.0, 0.0, 0.0))
+    spec = spec_of(pos, [r] * len(pos), params=prm, walls=walls, bodies=bodies)
+    b = O.OracleBed(spec)
+    b.step(1)
+    cs = b.last_contacts()
+    Fc, _, _ = b.last_contact_loads()
+    F = {int(i): Fc[q] for q, (i, j) in enumerate(cs.tolist()) if j < 0}
+    return prm, F, set(F)
+
+
+def test_annulus_face_and_rims_against_minimisation():
+    """A tilted, rotated annulus: spheres in front of its face, near the
+    inner and outer rim and behind it.  Contact iff the distance to the
+    annulus is below r (front side only); overlap and normal from the force."""
+    rng = np.random.default_rng(3)
+    R0 = rot_z(0.7) @ np.array([[1, 0, 0], [0, math.cos(0.4), -math.sin(0.4)], [0, math.sin(0.4), math.cos(0.4)]])
+    e0, e1, nu = R0[:, 0], R0[:, 1], R0[:, 2]
+    o = np.array([0.3, 0.4, 0.2])
+    rin, rout = 0.01, 0.02
+    r = R_SPH
+    pos, expect = [], []
+    for kind in range(40):
+        phi = rng.uniform(0, 2 * math.pi)
+        u = math.cos(phi) * e0 + math.sin(phi) * e1
+        if kind % 4 == 0:    # face
+            rho, s = rng.uniform(rin + 2e-3, rout - 2e-3), rng.uniform(0.2, 1.3) * r
+        elif kind % 4 == 1:  # outer rim
+            rho, s = rout + rng.uniform(-0.5, 1.2) * r, rng.uniform(0.05, 1.0) * r
+        elif kind % 4 == 2:  # inner rim
+            rho, s = rin - rng.uniform(-0.5, 1.2) * r, rng.uniform(0.05, 1.0) * r
+        else:                # behind the face: one-sided, never in contact
+            rho, s = rng.uniform(rin, rout), -rng.uniform(0.1, 0.9) * r
+        x = o + rho * u + s * nu
+        pos.append(x)
+    pos = np.array(pos)
+    walls = [beds.Wall(kind=beds.WALL_ANNULUS, body=1, origin=(0.0, 0.0, 0.0), axis=tuple(nu),
+                       frame=tuple(e0) + tuple(e1) + tuple(nu), dims=(rin, rout, 0.0))]
+    bodies = [beds.Body(), beds.Body(origin=tuple(o))]
+    prm, F, hit = one_step_wall_loads(pos, r, walls, bodies)
+    kn = kn_wall(prm, r)
+    n_contact = 0
+    for i, x in enumerate(pos):
+        front = (x - o) @ nu > 0
+        dist, q = annulus_distance(x, o, e0, e1, rin, rout)
+        if not front or dist >= r * (1 - 1e-9):
+            assert i not in hit or (front and abs(dist - r) < 1e-9 * r), (i, dist)
+            continue
+        n_contact += 1
+        assert i in hit, (i, dist)
+        Fn = np.linalg.norm(F[i])
+        delta = (Fn / kn) ** (2.0 / 3.0)
+        assert abs(delta - (r - dist)) < 1e-9 * r, (i, delta, r - dist)
+        n_exp = (q - x) / dist
+        np.testing.assert_allclose(-F[i] / Fn, n_exp, atol=1e-6)
+    assert n_contact >= 15
+
+
+def test_box_faces_edges_corners_against_minimisation():
+    """A rotated box: spheres off its faces, edges and corners, and inside.
+    Contact iff the distance is below r (inside: overlap r + depth)."""
+    rng = np.random.default_rng(5)
+    A = rot_z(0.3) @ np.array([[1, 0, 0], [0, math.cos(0.5), -math.sin(0.5)], [0, math.sin(0.5), math.cos(0.5)]])
+    axes = A.T  # rows are the box's local axes
+    o = np.array([0.5, 0.5, 0.3])
+    half = np.array([0.025, 0.0045, 0.0075])
+    r = R_SPH
+    pos = []
+    for kind in range(60):
+        sgn = rng.choice([-1.0, 1.0], 3)
+        l = rng.uniform(-1, 1, 3) * half
+        if kind % 4 == 0:    # face
+            a = rng.integers(3)
+            l[a] = sgn[a] * (half[a] + rng.uniform(-0.3, 1.2) * r)
+        elif kind % 4 == 1:  # edge
+            a, b2 = rng.choice(3, 2, replace=False)
+            l[a] = sgn[a] * (half[a] + rng.uniform(0.0, 0.8) * r)
+            l[b2] = sgn[b2] * (half[b2] + rng.uniform(0.0, 0.8) * r)
+        elif kind % 4 == 2:  # corner
+            l = sgn * (half + rng.uniform(0.0, 0.7, 3) * r)
+        else:                # inside, near a face
+            a = rng.integers(3)
+            l = rng.uniform(-0.8, 0.8, 3) * half
+            l[a] = sgn[a] * (half[a] - rng.uniform(0.05, 0.5) * r)
+        pos.append(o + axes.T @ l)
+    pos = np.array(pos)
+    walls = [beds.Wall(kind=beds.WALL_BOX, body=1, origin=(0.0, 0.0, 0.0), frame=tuple(axes.ravel()),
+                       dims=tuple(half))]
+    bodies = [beds.Body(), beds.Body(origin=tuple(o))]
+    prm, F, hit = one_step_wall_loads(pos, r, walls, bodies)
+    kn = kn_wall(prm, r)
+    n_contact = 0
+    for i, x in enumerate(pos):
+        dist, q = box_distance(x, o, axes, half)
+        if dist >= r * (1 - 1e-9):
+            assert i not in hit or abs(dist - r) < 1e-9 * r
+            continue
+        n_contact += 1
+        assert i in hit, (i, dist)
+        Fn = np.linalg.norm(F[i])
+        delta = (Fn / kn) ** (2.0 / 3.0)
+        assert abs(delta - (r - dist)) < 1e-9 * r, (i, delta, r - dist)
+        n_exp = (q - x) / np.linalg.norm(q - x)
+        if dist < 0:  # inside: pushed out through the nearest face
+            n_exp = -n_exp
+        np.testing.assert_allclose(-F[i] / Fn, n_exp, atol=1e-6)
+    assert n_contact >= 25
+
+
+def test_wall_pose_is_the_body_rotation():
+    """A box and an annulus on a body that translates and spins: at clock k
+    the world pose is origin(t) + R_z(Omega t) (body-frame geometry)."""
+    c0, vel, Om, dt = np.array([0.1, 0.2, 0.3]), np.array([0.01, -0.02, 0.005]), 0.7, 2e-6
+    box_o, ann_o = np.array([0.03, 0.01, -0.002]), np.array([0.0, 0.0, 0.001])
+    frame = rot_z(0.2).T
+    walls = [beds.Wall(kind=beds.WALL_BOX, body=1, origin=tuple(box_o), frame=tuple(frame.ravel()),
+                       dims=(0.01, 0.002, 0.003)),
+             beds.Wall(kind=beds.WALL_ANNULUS, body=1, origin=tuple(ann_o), axis=(0.0, 0.0, -1.0),
+                       frame=(1, 0, 0, 0, 1, 0, 0, 0, -1), dims=(0.1, 0.15, 0.0))]
+    spec = spec_of([[0.9, 0.9, 0.9]], [R_SPH], params=beds.Params(dt=dt), walls=walls,
+                   bodies=[beds.Body(), beds.Body(origin=tuple(c0), lin_vel=tuple(vel), ang_vel=Om)])
+    b = O.OracleBed(spec)
+    for k in (0, 1, 777, 123456, 9_000_000):
+        b.set_clock(k)
+        t = k * dt
+        Rm = rot_z(Om * t)
+        c = c0 + vel * t
+        o, nu, e = b.wall_pose(0)
+        np.testing.assert_allclose(o, c + Rm @ box_o, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(e, (Rm @ frame.T).T, rtol=0, atol=1e-15)
+        o, nu, e = b.wall_pose(1)
+        np.testing.assert_allclose(o, c + Rm @ ann_o, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(nu, [0.0, 0.0, -1.0], rtol=0, atol=1e-15)
+        np.testing.assert_allclose(e[0], Rm @ [1.0, 0.0, 0.0], rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# moving walls: velocity at the contact point, slip torque
+
+def held_steps(b, pos, n):
+    """Steps n times with the spheres held at `pos` (zero velocity and spin)."""
+    z = np.zeros_like(pos)
+    for _ in range(n):
+        b.set_state(pos, z, z)
+        b.step(1)
+
+
+def test_spinning_wall_velocity_at_the_contact_point():
+    """A held sphere against a spinning box side (a grouser): after one step
+    the stored spring is dt times the tangential relative velocity, which is
+    minus the wall velocity Omega z x (p - c) at the contact point p (not at
+    the sphere centre); the normal force carries the damping term of that
+    velocity's normal part."""
+    r = R_SPH
+    Om, dt = 3.0, 2e-6
+    c = np.array([0.5, 0.5, 0.1])
+    half = np.array([0.004, 0.02, 0.01])
+    box_o = np.array([0.05, 0.0, 0.0])  # body frame; the box's +x face sits at x = 0.054
+    delta = 2e-6
+    x = c + np.array([0.054 + r - delta, 0.013, -0.002])
+    # mu_t large enough that the first step sticks (trial force below the cone)
+    prm = beds.Params(g=(0.0, 0.0, 0.0), dt=dt, mu_t=5.0, mu_r=0.0)
+    walls = [beds.Wall(kind=beds.WALL_BOX, body=1, origin=tuple(box_o), dims=tuple(half))]
+    spec = spec_of([x], [r], params=prm, walls=walls, bodies=[beds.Body(), beds.Body(origin=tuple(c), ang_vel=Om)])
+    b = O.OracleBed(spec)
+    held_steps(b, np.array([x]), 1)
+    n = np.array([-1.0, 0.0, 0.0])            # sphere centre -> wall
+    p = x + (r - 0.5 * delta) * n             # contact point
+    uw = np.cross([0.0, 0.0, Om], p - c)      # wall velocity at p
+    u = -uw                                   # sphere at rest
+    vt = u - (u @ n) * n
+    keys, vals = b.history()
+    assert keys.tolist() == [[0, -1]]
+    np.testing.assert_allclose(vals[0, :3], dt * vt, rtol=1e-12, atol=1e-24)
+    kn = kn_wall(prm, r)
+    gn = prm.gamma_factor * dt
+    Fn = kn * (delta ** 1.5 + 1.25 * gn * math.sqrt(delta) * (u @ n))
+    F, _ = b.last_forces()
+    assert abs(-(F[0] @ n) - Fn) < 1e-10 * Fn
+
+
+@pytest.mark.parametrize("Om", [0.5, -2.0])
+def test_slipping_sphere_torque_on_a_spinning_annulus(Om):
+    """A held sphere on an annulus floor spinning about +z: once the spring
+    saturates, the friction force is mu_t F_n along the wall's motion and the
+    reaction on the annulus is F_n down plus -mu_t F_n along the motion, with
+    torque (p - c) x R about the body origin: -sign(Omega) mu_t F_n r_c about z."""
+    r = R_SPH
+    dt = 2e-6
+    mu = 0.3
+    prm = beds.Params(g=(0.0, 0.0, 0.0), dt=dt, mu_t=mu, mu_r=0.0)
+    c = np.array([0.4, 0.4, 0.05])
+    phi, rc, delta = 1.1, 0.12, 3e-6
+    x = c + np.array([rc * math.cos(phi), rc * math.sin(phi), r - delta])
+    walls = [beds.Wall(kind=beds.WALL_ANNULUS, body=1, axis=(0.0, 0.0, 1.0), dims=(0.10, 0.15, 0.0))]
+    spec = spec_of([x], [r], params=prm, walls=walls, bodies=[beds.Body(), beds.Body(origin=tuple(c), ang_vel=Om)])
+    b = O.OracleBed(spec)
+    held_steps(b, np.array([x]), 400)
+    Fn = kn_wall(prm, r) * delta ** 1.5
+    t_hat = np.sign(Om) * np.array([-math.sin(phi), math.cos(phi), 0.0])  # direction of the wall's motion at p
+    F, _ = b.last_forces()
+    np.testing.assert_allclose(F[0], [0.0, 0.0, Fn] + mu * Fn * t_hat, rtol=0, atol=1e-9 * Fn)
+    R = b.last_reaction(1)
+    p = x - (r - 0.5 * delta) * np.array([0.0, 0.0, 1.0])
+    Fb = np.array([0.0, 0.0, -Fn]) - mu * Fn * t_hat
+    np.testing.assert_allclose(R[:3], Fb, rtol=0, atol=1e-9 * Fn)
+    np.testing.assert_allclose(R[3:], np.cross(p - c, Fb), rtol=0, atol=1e-9 * Fn * rc)
+    assert abs(R[5] - (-np.sign(Om) * mu * Fn * rc)) < 1e-9 * Fn * rc
+
+
+def test_body_reaction_force_and_torque_at_a_known_lever():
+    """Two held spheres under a plate body whose origin is offset from them:
+    the reaction is the sum of their Hertz forces (up) and the torque is
+    sum (p - c) x F about the body origin, plus the reaction to a
+    rolling-resistance moment of a spinning sphere (+mu_r r F_n about its
+    spin axis: the particle's moment opposes its spin)."""
+    r = R_SPH
+    dt = 2e-6
+    mu_r = 1e-4   # small enough that the rolling moment is at its cap from the first step
+    prm = beds.Params(g=(0.0, 0.0, 0.0), dt=dt, mu_t=0.3, mu_r=mu_r)
+    c = np.array([0.2, 0.3, 0.05])
+    d1, d2 = 2e-6, 4.5e-6
+    x = np.array([[0.23, 0.31, 0.05 - r + d1], [0.17, 0.26, 0.05 - r + d2]])
+    w = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 40.0]])
+    walls = [beds.Wall(kind=beds.WALL_PLANE, body=1, axis=(0.0, 0.0, -1.0))]
+    spec = spec_of(x, [r, r], omg=w, params=prm, walls=walls, bodies=[beds.Body(), beds.Body(origin=tuple(c))])
+    b = O.OracleBed(spec)
+    b.step(1)
+    kn = kn_wall(prm, r)
+    R = b.last_reaction(1)
+    F_exp = np.zeros(3)
+    T_exp = np.zeros(3)
+    for q, d in enumerate((d1, d2)):
+        Fn = kn * d ** 1.5
+        p = x[q] + (r - 0.5 * d) * np.array([0.0, 0.0, 1.0])
+        Fb = np.array([0.0, 0.0, Fn])
+        F_exp += Fb
+        T_exp += np.cross(p - c, Fb)
+        if q == 1:
+            T_exp += mu_r * r * Fn * np.array([0.0, 0.0, 1.0])
+    np.testing.assert_allclose(R[:3], F_exp, rtol=1e-12)
+    np.testing.assert_allclose(R[3:], T_exp, rtol=1e-10, atol=1e-14)
+    # the particle side of the rolling moment
+    _, T = b.last_forces()
+    Fn2 = kn * d2 ** 1.5
+    assert abs(T[1, 2] - (-mu_r * r * Fn2)) < 1e-10 * mu_r * r * Fn2
+
+
+# ---------------------------------------------------------------------------
+# dead-weight bodies
+
+def test_dead_weight_free_fall_is_the_discrete_sum():
+    """A z-free body with nothing under it: semi-implicit Euler gives
+    v_k = v0 - k g dt and z_k = z0 + k v0 dt - g dt^2 k (k + 1) / 2."""
+    dt, g = 2e-6, 9.81
+    z0, v0 = 0.3, 0.02
+    walls = [beds.Wall(kind=beds.WALL_PLANE, body=1, axis=(0.0, 0.0, -1.0))]
+    spec = spec_of([[0.5, 0.5, 0.01]], [R_SPH], params=beds.Params(dt=dt), walls=walls,
+                   bodies=[beds.Body(), beds.Body(origin=(0.0, 0.0, z0), lin_vel=(0.0, 0.0, v0), z_free=1, mass=2.0)])
+    b = O.OracleBed(spec)
+    k = 1000
+    b.step(k)
+    o, v = b.body_state(1)
+    assert abs(v[2] - (v0 - k * g * dt)) < 1e-15
+    # k additions to z ~ 0.3 round by up to k ulp (5.6e-17 each); using the old velocity
+    # instead of the new one would be off by g dt^2 k ~ 4e-8
+    assert abs(o[2] - (z0 + k * v0 * dt - g * dt * dt * k * (k + 1) / 2)) < 1e-13
+
+
+def test_dead_weight_resting_on_a_hertz_column():
+    """A z-free plate of mass M on a sphere on the floor, both at the Hertz
+    equilibrium of their loads: the plate's reaction is M g and it stays at
+    rest; raised by a fraction of its overlap it accelerates down."""
+    r = R_SPH
+    dt, g = 2e-6, 9.81
+    prm = beds.Params(rho=2600.0, dt=dt)
+    M = 1e-3
+    m = prm.rho * 4.0 / 3.0 * math.pi * r ** 3
+    kn = kn_wall(prm, r)
+    df = ((M + m) * g / kn) ** (2.0 / 3.0)   # floor overlap under sphere + plate
+    dp = (M * g / kn) ** (2.0 / 3.0)         # plate overlap
+    zs = r - df
+    zp = zs + r - dp
+    walls = [beds.floor_wall(), beds.Wall(kind=beds.WALL_PLANE, body=1, axis=(0.0, 0.0, -1.0))]
+
+    def run(z_plate, steps):
+        spec = spec_of([[0.5, 0.5, zs]], [r], params=prm, walls=walls,
+                       bodies=[beds.Body(), beds.Body(origin=(0.5, 0.5, z_plate), z_free=1, mass=M)])
+        b = O.OracleBed(spec)
+        b.step(steps)
+        return b
+
+    b = run(zp, 1)
+    R = b.last_reaction(1)
+    assert abs(R[2] - M * g) < 1e-9 * M * g
+    _, v = b.body_state(1)
+    assert abs(v[2]) < 1e-12
+    b.step(2000)
+    o, v = b.body_state(1)
+    assert abs(o[2] - zp) < 1e-3 * dp and abs(v[2]) < 1e-6
+    b = run(zp + 0.5 * dp, 1)
+    _, v = b.body_state(1)
+    R = b.last_reaction(1)
+    assert 0.0 < R[2] < M * g and v[2] < 0.0
+    assert abs(v[2] - dt * (R[2] / M - g)) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# the tangential spring follows the contact frame
+
+@pytest.mark.parametrize("dtheta", [0.01, 0.03])
+@pytest.mark.parametrize("axial", [0.0, 0.4])
+def test_stuck_spring_co_rotates_with_a_rigid_pair(dtheta, axial):
+    """Two touching spheres held on a rigid rotation about z through their
+    midpoint (velocities Omega z x (x - c), spins Omega z): the relative
+    velocity at the contact point is zero, so a stuck spring must turn with
+    the pair and keep its length.  A spring in the plane of the rotation is
+    then exactly R_z(theta) applied to its start value after the step at pose
+    angle theta.  A spring with a part along the rotation axis keeps its
+    length exactly, while moving it into the new tangent plane (project,
+    then rescale to the old length) turns it by the frame's rotation only to
+    first order: its direction may drift by O(dtheta^2) per step."""
+    r = R_SPH
+    dt = 2e-6
+    Om = dtheta / dt
+    delta = 2e-6
+    prm = beds.Params(g=(0.0, 0.0, 0.0), dt=dt, mu_t=0.5, mu_r=0.02, rho=1e15)
+    c = np.array([0.5, 0.5, 0.5])
+    half = r - 0.5 * delta
+
+    def pose(th):
+        u = np.array([math.cos(th), math.sin(th), 0.0])
+        x = np.array([c - half * u, c + half * u])
+        v = np.cross([0.0, 0.0, Om], x - c)
+        w = np.tile([0.0, 0.0, Om], (2, 1))
+        return x, v, w
+
+    x0, v0, w0 = pose(0.0)
+    spec = spec_of(x0, [r, r], params=prm)
+    b = O.OracleBed(spec)
+    xi0 = 0.01 * delta * np.array([0.0, 1.0, axial])  # in the tangent plane at theta = 0
+    b.set_history(np.array([[0, 1]]), np.array([[*xi0, 0.0, 0.0, 0.0]]))
+    L0 = np.linalg.norm(xi0)
+    for k in range(40):
+        th = k * dtheta
+        x, v, w = pose(th)
+        b.set_state(x, v, w)
+        b.step(1)
+        keys, vals = b.history()
+        assert keys.tolist() == [[0, 1]]
+        xi = vals[0, :3]
+        n = np.array([math.cos(th), math.sin(th), 0.0])
+        assert abs(xi @ n) < 1e-12 * L0                      # in the current tangent plane
+        assert abs(np.linalg.norm(xi) - L0) < 1e-12 * L0     # length kept
+        if axial == 0.0:
+            np.testing.assert_allclose(xi, rot_z(th) @ xi0, rtol=0, atol=1e-12 * L0)
+        else:
+            np.testing.assert_allclose(xi, rot_z(th) @ xi0, rtol=0, atol=(k + 1) * dtheta ** 2 * L0)
+        np.testing.assert_allclose(vals[0, 3:], 0.0, atol=1e-25)
