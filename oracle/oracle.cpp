@@ -368,7 +368,7 @@ void grid_pairs(const orc_bed& b, const std::vector<V3<double>>& x, std::vector<
     cells[c].push_back(i);
   }
   std::vector<std::vector<Contact>> per_owner((size_t)b.n);
-#pragma omp parallel for schedule(dynamic, 256)
+#pragma omp parallel for schedule(dynamic, 256) if (b.n > 4096)
   for (int64_t i = 0; i < b.n; ++i) {
     int64_t ci[3] = {cell_of(x[i], 0), cell_of(x[i], 1), cell_of(x[i], 2)};
     std::vector<int64_t> nb[3];
@@ -579,7 +579,7 @@ T step_once(orc_bed& b, State<T>& S, int rbody, int comp = 2) {
 
   const int64_t nc = (int64_t)cs.size();
   std::vector<LawOut<T>> lo((size_t)nc);
-#pragma omp parallel for schedule(dynamic, 1024)
+#pragma omp parallel for schedule(dynamic, 1024) if (nc > 4096)
   for (int64_t q = 0; q < nc; ++q) lo[q] = eval_contact(b, S, wp, bp, cs[q]);
 
   const V3<T> zero = {T(0.0), T(0.0), T(0.0)};
@@ -633,7 +633,7 @@ T step_once(orc_bed& b, State<T>& S, int rbody, int comp = 2) {
   // semi-implicit Euler: v first, then x with the new v; wrap periodic axes
   const double dt = b.p.dt;
   const V3<T> g = {T(b.p.g[0]), T(b.p.g[1]), T(b.p.g[2])};
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (b.n > 4096)
   for (int64_t i = 0; i < b.n; ++i) {
     const V3<T> a = add(scl(T(1.0 / b.m[i]), F[i]), g);
     S.v[i] = add(S.v[i], scl(T(dt), a));
@@ -802,7 +802,7 @@ void spook_step(orc_bed& b) {
   };
   rebuild();
   for (int it = 0; it < b.n_iter; ++it) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (nc > 4096)
     for (int64_t q = 0; q < nc; ++q) {
       SpC& c = C[q];
       const int64_t i = c.a;
