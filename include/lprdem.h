@@ -134,9 +134,22 @@ typedef struct {
   int32_t block;           /* threads per block of the step kernel: 64, 128
                               or 256 (0: 256) */
   int32_t record_forces;   /* 1: keep the last step's per-particle contact
-                              forces and torques for lpr_read_forces */
+                              forces and torques for lpr_read_forces and its
+                              per-contact loads for lpr_read_contact_loads
+                              (64 B per particle and owner slot, 32 B per
+                              particle and wall) */
   int32_t persistent;      /* 1: the step kernel runs as one persistent grid
                               that fills the GPU (same results) */
+  /* storage order (never changes results, only which particles share cache
+     lines): particles are kept sorted by (level, Morton code of their cell),
+     equal codes in their previous order.  At every sort_every-th rebuild a
+     device radix sort re-sorts them and the state is gathered into the new
+     order; 0: the default (every 16th rebuild with rebuild_every 1, every
+     rebuild otherwise), < 0: never (the order of creation stays), at most
+     4096 */
+  int32_t sort_every;
+  int32_t input_order;     /* 1: start from the caller's order instead of the
+                              sorted one (to measure what the sort buys) */
 } lpr_bed_desc;
 
 #define LPR_MAX_WALLS 16
@@ -161,8 +174,9 @@ typedef struct lpr_bed lpr_bed;
 /* Creates a bed.  The description is validated (0 < n < 2^27, r > 0,
  * finite inputs, dt > 0, periodic length > 2 max(r_i + r_j + skin),
  * wall/body indices in range), particles are placed in Morton order per
- * radius band on the device, and the per-step kernel sequence is captured in
- * a HIP graph on `hip_stream` (NULL = the default stream).  *out receives
+ * radius band on the device (and re-sorted there as they move, see
+ * sort_every), and the per-step kernel sequence is captured in a HIP graph
+ * on `hip_stream` (NULL = the default stream).  *out receives
  * the bed; on error *out is NULL.  A sphere owns its contacts with spheres
  * of larger radius (equal radii: larger stable id) in 16 slots; a 17th
  * latches LPR_E_CAPACITY, reported at the next lpr_sync. */
@@ -179,6 +193,15 @@ lpr_status lpr_step(lpr_bed* bed, int64_t n_steps);
  * reduction kernel, out[3]: ms from the first to the last event.  Used to
  * measure per-kernel durations for the roofline. */
 lpr_status lpr_step_profiled(lpr_bed* bed, int64_t n_steps, double out[4]);
+/* Like lpr_step_profiled with finer phases, HIP events on the bed's stream
+ * at each phase boundary of every step, then waits.  Summed milliseconds:
+ * out[0] binning (counter clearing, cell binning and the cell-range scan),
+ * out[1] re-sort of the storage order (radix sort and gather; 0 in steps
+ * without one), out[2] cell lists, out[3] owner-side search, out[4] reverse
+ * lists, out[5] the contact step (the fused kernel, or the implicit step's
+ * kernels), out[6] body reduction, out[7] ms from the first to the last
+ * event.  Phases 0-4 are 0 in steps that reuse candidate lists. */
+lpr_status lpr_step_phases(lpr_bed* bed, int64_t n_steps, double out[8]);
 /* Waits for the bed's stream and reports any latched device status. */
 lpr_status lpr_sync(lpr_bed* bed);
 
@@ -202,6 +225,30 @@ lpr_status lpr_read_contacts(lpr_bed* bed, lpr_contact* out, int64_t capacity, i
 /* The last step's contact-only force and torque per particle (requires
  * record_forces; host buffers n*3, stable-id order). */
 lpr_status lpr_read_forces(lpr_bed* bed, float* force, float* torque);
+/* Loads of one contact of the last step (section "Nonsmooth DEM and
+ * multibody dynamics", eq:g_n, eq:G_t, eq:G_r): a and b as in lpr_contact;
+ * force = the contact force on particle a (normal and tangential parts),
+ * moment = the rolling-resistance moment on particle a (the torque on a is
+ * (p - x_a) x force + moment, p the contact point), fn = the normal force
+ * magnitude F_n >= 0.  For a wall contact (b = -1 - w) they act on the
+ * particle. */
+typedef struct {
+  int64_t a, b;
+  float force[3];
+  float moment[3];
+  float fn;
+  float reserved;
+} lpr_contact_load;
+
+/* The last step's per-contact loads in lpr_read_contacts order (requires
+ * record_forces and the explicit stepper, else LPR_E_STATE); LPR_E_CAPACITY
+ * with *n_total set and nothing written when capacity is too small. */
+lpr_status lpr_read_contact_loads(lpr_bed* bed, lpr_contact_load* out, int64_t capacity, int64_t* n_total);
+/* World pose of wall `wall` at the current clock (the pose the next step
+ * uses): origin (3), unit normal `axis` after the body's motion (3), and the
+ * three rows of its frame (9).  The body rotation angle is ang_vel * k dt
+ * in FP64 (cos and sin of the device math library). */
+lpr_status lpr_read_wall_pose(lpr_bed* bed, int32_t wall, double out15[15]);
 /* Reaction of the last step on a body: force from the particles (3) and
  * torque about the body origin (3), FP64. */
 lpr_status lpr_read_reaction(lpr_bed* bed, int32_t body, double out6[6]);
@@ -228,6 +275,7 @@ typedef struct {
                                (those steps were rebuilt and repeated) */
   int32_t adjoint_interval; /* checkpoint interval of the last adjoint window
                                (0 before the first) */
+  int64_t sorts;            /* device re-sorts of the storage order */
 } lpr_stats;
 lpr_status lpr_get_stats(lpr_bed* bed, lpr_stats* out);
 
@@ -253,6 +301,9 @@ lpr_status lpr_batch_set_history(lpr_bed* batch, int32_t bed, const lpr_history*
 lpr_status lpr_batch_read_contacts(lpr_bed* batch, int32_t bed, lpr_contact* out, int64_t capacity,
                                    int64_t* n_total);
 lpr_status lpr_batch_read_forces(lpr_bed* batch, int32_t bed, float* force, float* torque);
+lpr_status lpr_batch_read_contact_loads(lpr_bed* batch, int32_t bed, lpr_contact_load* out, int64_t capacity,
+                                        int64_t* n_total);
+lpr_status lpr_batch_read_wall_pose(lpr_bed* batch, int32_t bed, int32_t wall, double out15[15]);
 lpr_status lpr_batch_read_reaction(lpr_bed* batch, int32_t bed, int32_t body, double out6[6]);
 lpr_status lpr_batch_reaction_window(lpr_bed* batch, int32_t bed, int32_t body, double sum6[6], int64_t* steps,
                                      int32_t reset);

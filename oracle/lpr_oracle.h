@@ -119,6 +119,13 @@ int orc_last_reaction(const orc_bed* b, int32_t body, double out6[6]);
  * owner (3) and the normal force magnitude F_n >= 0 (1).  Under the implicit
  * stepper these are impulses / dt.  Any pointer may be NULL. */
 int orc_last_contact_loads(const orc_bed* b, double* force3, double* moment3, double* fn);
+/* Per contact of the last explicit step, in orc_last_contacts order: the
+ * summed magnitudes of the contact law's force terms (elastic and damping
+ * normal terms, tangential spring and damping terms) and of its moment
+ * terms (rolling spring and damping), before they combine and are capped:
+ * the scales that rounding in an evaluation of the law is relative to.
+ * Either pointer may be NULL. */
+int orc_last_contact_scales(const orc_bed* b, double* force_terms, double* moment_terms);
 /* World pose of wall `wall` at the current clock (the pose the next step
  * uses): origin (3), normal (3), the three rows of its frame (9). */
 int orc_wall_pose(const orc_bed* b, int32_t wall, double out15[15]);

@@ -156,6 +156,10 @@ struct orc_bed {
   // per contact of the last step, in last_contacts order: force on the
   // owner (3), rolling moment on the owner (3), normal force magnitude
   std::vector<double> lastCF, lastCM, lastCN;
+  // per contact of the last step: the summed magnitudes of the law's force
+  // terms (elastic, damping, tangential spring and damping) and of its
+  // moment terms (rolling spring and damping) before they combine
+  std::vector<double> lastCSF, lastCSM;
   int stepper = 0;      // 0: explicit compliant step, 1: SPOOK with projected iterations
   int n_iter = 0;       // projected iterations per SPOOK step
 };
@@ -426,6 +430,7 @@ struct LawOut {
   V3<T> Mr;        // rolling-resistance moment on the owner
   V3<T> p;         // contact point (world, owner's image frame)
   T Fn;            // normal force magnitude (after the clamp at zero)
+  double sF, sM;   // magnitudes of the law's force and moment terms
   std::array<T, 6> xi;
 };
 
@@ -442,7 +447,7 @@ struct LawIn {
 
 template <class T>
 void contact_law(const orc_params& p, const T& s_k, const LawIn<T>& in, V3<T>* F_out, V3<T>* M_out,
-                 std::array<T, 6>* xi_new, T* Fn_out) {
+                 std::array<T, 6>* xi_new, T* Fn_out, double* scale_F, double* scale_M) {
   const double eH = p.e_H;
   const double Estar = 1.0 / ((1.0 - p.nu * p.nu) / p.E + (1.0 - p.nu * p.nu) / p.E);
   const double rstar = 0.5 * in.dstar;
@@ -467,6 +472,8 @@ void contact_law(const orc_params& p, const T& s_k, const LawIn<T>& in, V3<T>* F
   if (val(len_p) > 0.0) xp = scl(len_old / len_p, xp);
   xt = add(xp, scl(T(p.dt), vt));
   V3<T> Ft = sub(scl(-kt, xt), scl(ct, vt));
+  *scale_F = std::fabs(val(kn * a1)) + std::fabs(val(kn * T(eH * gn) * a0 * ddelta)) + val(kt) * val(norm(xt)) +
+             val(ct) * val(norm(vt));
   const T Ftn = norm(Ft);
   const T capt = in.mu_t * Fn;
   if (val(Ftn) > val(capt)) {
@@ -479,6 +486,7 @@ void contact_law(const orc_params& p, const T& s_k, const LawIn<T>& in, V3<T>* F
   V3<T> xr = {in.xi_old[3], in.xi_old[4], in.xi_old[5]};
   xr = add(xr, scl(T(p.dt), in.wrel));
   V3<T> Mr = sub(scl(-kr, xr), scl(cr, in.wrel));
+  *scale_M = val(kr) * val(norm(xr)) + val(cr) * val(norm(in.wrel));
   const T Mrn = norm(Mr);
   const T capr = in.mu_r * T(rstar) * Fn;
   if (val(Mrn) > val(capr)) {
@@ -531,7 +539,7 @@ LawOut<T> eval_contact(const orc_bed& b, const State<T>& S, const std::vector<Wa
     in.mu_t = S.mu_t;
     in.mu_r = S.mu_r;
     V3<T> F, M;
-    contact_law(b.p, S.s_k, in, &F, &M, &out.xi, &out.Fn);
+    contact_law(b.p, S.s_k, in, &F, &M, &out.xi, &out.Fn, &out.sF, &out.sM);
     out.Fi = F;
     out.Mr = M;
     out.Ti = add(cross(ai, F), M);
@@ -557,7 +565,7 @@ LawOut<T> eval_contact(const orc_bed& b, const State<T>& S, const std::vector<Wa
   in.mu_t = (W.mu_t < 0.0) ? S.mu_t : T(W.mu_t);
   in.mu_r = (W.mu_r < 0.0) ? S.mu_r : T(W.mu_r);
   V3<T> F, M;
-  contact_law(b.p, S.s_k, in, &F, &M, &out.xi, &out.Fn);
+  contact_law(b.p, S.s_k, in, &F, &M, &out.xi, &out.Fn, &out.sF, &out.sM);
   out.Fi = F;
   out.Mr = M;
   out.Ti = add(cross(ai, F), M);
@@ -620,7 +628,11 @@ T step_once(orc_bed& b, State<T>& S, int rbody, int comp = 2) {
   b.lastCF.assign((size_t)(3 * nc), 0.0);
   b.lastCM.assign((size_t)(3 * nc), 0.0);
   b.lastCN.assign((size_t)nc, 0.0);
+  b.lastCSF.assign((size_t)nc, 0.0);
+  b.lastCSM.assign((size_t)nc, 0.0);
   for (int64_t q = 0; q < nc; ++q) {
+    b.lastCSF[q] = lo[q].sF;
+    b.lastCSM[q] = lo[q].sM;
     b.lastCF[3 * q + 0] = val(lo[q].Fi.x); b.lastCF[3 * q + 1] = val(lo[q].Fi.y); b.lastCF[3 * q + 2] = val(lo[q].Fi.z);
     b.lastCM[3 * q + 0] = val(lo[q].Mr.x); b.lastCM[3 * q + 1] = val(lo[q].Mr.y); b.lastCM[3 * q + 2] = val(lo[q].Mr.z);
     b.lastCN[q] = val(lo[q].Fn);
@@ -853,6 +865,8 @@ void spook_step(orc_bed& b) {
   b.lastCF.assign((size_t)(3 * nc), 0.0);
   b.lastCM.assign((size_t)(3 * nc), 0.0);
   b.lastCN.assign((size_t)nc, 0.0);
+  b.lastCSF.clear();  // the explicit law's term scales do not apply
+  b.lastCSM.clear();
   std::vector<std::vector<int64_t>> nk((size_t)b.n);
   std::vector<std::vector<Hist>> nv((size_t)b.n);
   for (int64_t q = 0; q < nc; ++q) {
@@ -1112,6 +1126,14 @@ int orc_last_contact_loads(const orc_bed* b, double* force3, double* moment3, do
   if (force3 && nc) std::memcpy(force3, b->lastCF.data(), sizeof(double) * 3 * nc);
   if (moment3 && nc) std::memcpy(moment3, b->lastCM.data(), sizeof(double) * 3 * nc);
   if (fn && nc) std::memcpy(fn, b->lastCN.data(), sizeof(double) * nc);
+  return 0;
+}
+
+int orc_last_contact_scales(const orc_bed* b, double* force_terms, double* moment_terms) {
+  if (!b || b->lastCSF.size() != b->last_contacts.size()) return -1;
+  const size_t nc = b->last_contacts.size();
+  if (force_terms && nc) std::memcpy(force_terms, b->lastCSF.data(), sizeof(double) * nc);
+  if (moment_terms && nc) std::memcpy(moment_terms, b->lastCSM.data(), sizeof(double) * nc);
   return 0;
 }
 

@@ -64,6 +64,7 @@ def lib():
                            ("orc_last_forces", [vp, vp, vp]), ("orc_last_reaction", [vp, i32, vp]),
                            ("orc_tangent_window", [vp, i64, i32, i32, vp, vp]),
                            ("orc_last_contact_loads", [vp, vp, vp, vp]), ("orc_wall_pose", [vp, i32, vp]),
+                           ("orc_last_contact_scales", [vp, vp, vp]),
                            ("orc_set_stepper", [vp, i32, i32])]:
             f = getattr(L, name)
             f.restype = ctypes.c_int
@@ -208,6 +209,14 @@ class OracleBed:
         F = np.zeros((max(k, 1), 3)); M = np.zeros((max(k, 1), 3)); fn = np.zeros(max(k, 1))
         self._ok(lib().orc_last_contact_loads(self._h, _ptr(F), _ptr(M), _ptr(fn)), "last_contact_loads")
         return F[:k], M[:k], fn[:k]
+
+    def last_contact_scales(self):
+        """Per contact of the last explicit step (last_contacts order): the
+        summed magnitudes of the law's force terms and of its moment terms."""
+        k = len(self.last_contacts())
+        sF = np.zeros(max(k, 1)); sM = np.zeros(max(k, 1))
+        self._ok(lib().orc_last_contact_scales(self._h, _ptr(sF), _ptr(sM)), "last_contact_scales")
+        return sF[:k], sM[:k]
 
     def wall_pose(self, wall):
         """World pose of a wall at the current clock: origin, normal, frame (3 x 3 rows)."""

@@ -88,6 +88,7 @@ struct BedConst {
   float dt;
   float g[3];
   int32_t law;           // 0: e_H = 5/4, 1: e_H = 1, 2: general
+  int32_t sort_off;      // storage index of a particle minus its rank in the sorted order of all beds
   double dt_d;
 };
 
@@ -131,6 +132,37 @@ struct BedDyn {
   int64_t k;           // step index of the next step (t = k dt)
   int64_t completed;   // completed steps since creation
 };
+
+// Number of cells of an n[0] x n[1] x n[2] grid whose Morton code (bits of
+// x, y, z interleaved, x lowest) is below that of cell c: the cell's rank in
+// the Morton order of the grid, dense in [0, cells).  For every bit of c's
+// code that is set, the cells sharing the code above that bit and having 0
+// there are counted axis by axis: each axis then has some high bits fixed and
+// its low bits free, and the count is the part of that range inside the grid.
+__host__ __device__ inline int64_t morton_rank(const int32_t c[3], const int32_t n[3]) {
+  const int32_t m = n[0] > n[1] ? (n[0] > n[2] ? n[0] : n[2]) : (n[1] > n[2] ? n[1] : n[2]);
+  int nb = 0;
+  while ((1 << nb) < m) ++nb;
+  int64_t rank = 0;
+  for (int k = nb - 1; k >= 0; --k)
+    for (int a = 2; a >= 0; --a) {
+      if (!((c[a] >> k) & 1)) continue;
+      int64_t prod = 1;
+      for (int b = 0; b < 3; ++b) {
+        // axes below a keep bit k free, axes above it have it fixed, axis a
+        // has it fixed to 0
+        const int sh = (b > a) ? k : k + 1;
+        const int w = (b < a) ? k + 1 : k;
+        const int64_t lo = (int64_t)(c[b] >> sh) << sh;
+        int64_t cnt = (int64_t)n[b] - lo;
+        const int64_t cap = (int64_t)1 << w;
+        cnt = cnt < 0 ? 0 : (cnt > cap ? cap : cnt);
+        prod *= cnt;
+      }
+      rank += prod;
+    }
+  return rank;
+}
 
 // ---------------------------------------------------------------------------
 // Exact FP64 geometry.  These expressions are the contact-set definition;
@@ -282,6 +314,7 @@ struct LawOut {
   float3 Ft;         // its tangential part
   float3 M;          // rolling moment on the owner
   float3 xt, xr;     // updated springs
+  float Fn;          // normal force magnitude (after the clamp at zero)
 };
 
 // Intermediates of one law evaluation: everything its vector-Jacobian
@@ -357,6 +390,7 @@ __device__ __forceinline__ void law_forward(const BedConst& bc, const LawIn& in,
     o.xr = t.xr1;
   }
   o.F = o.Ft - t.Fn * in.n;
+  o.Fn = t.Fn;
 }
 
 __device__ __forceinline__ void contact_law(const BedConst& bc, const LawIn& in, LawOut& o) {

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "lpr_dev.h"
+#include "lprdem.h"
 
 namespace lpr {
 
@@ -39,6 +40,11 @@ struct DevBufs {
   // records
   float4* frc;           // optional
   float4* trq;
+  float4* cF;            // optional, [K][N]: per owner slot in contact, force on the owner and F_n
+  float4* cM;            // optional, [K][N]: rolling moment on the owner
+  float4* wF;            // optional, [nwall_max][N]: the same per wall contact
+  float4* wM;
+  int32_t nwall_max;
   double* partial;       // [bodies][6][nblk] block partial sums of reactions
   int64_t nblk;          // blocks of the smallest step-kernel block size (N / 64)
   // scan scratch
@@ -47,6 +53,13 @@ struct DevBufs {
   float4* cpf;           // FP32 (x, y, z, r) in cell-list order (rebuild)
   uint32_t* zext;        // [levels][2] highest z and highest -z of the level's centres seen
                          // (order-preserving FP32 bits, 0 = none; monotone)
+  // storage-order sort (radix sort of (level, Morton) keys)
+  uint32_t* skey[2];     // [N] keys, ping-pong over the passes
+  int32_t* sval[2];      // [N] storage indices carried with the keys
+  uint32_t* rs_hist;     // [256 * tiles + 1] digit counts per tile, then their scan
+  int32_t* src;          // [N] after a sort: previous storage index of each particle
+  int32_t sort_bits;     // key bits (keys are < 2^sort_bits)
+  int64_t n_active;      // particles of all beds (the sorted ranks that are real)
   float* disp;           // distance bound moved since the last rebuild
   uint32_t* viol;        // [2] skin-exceeded flags, by state parity
   // tables
@@ -98,12 +111,23 @@ struct StepPar {
 };
 
 void launch_zero(uint32_t* p, int64_t n, hipStream_t st);
-void launch_bin(const DevBufs& d, int s, hipStream_t st);
+// sort = 1 also writes each particle's sort key (level base + Morton rank
+// of its cell) and storage index.
+void launch_bin(const DevBufs& d, int s, int sort, hipStream_t st);
+// Stable LSD radix sort of (skey[0], sval[0]) in 8-bit digits; the result is
+// in buffer (passes & 1).  Returns the number of passes.
+int launch_sort(const DevBufs& d, hipStream_t st);
+size_t sort_hist_elems(int64_t n);
+// Gathers the particles into sorted order: state s into st_out, stable id,
+// metadata, cell and cell rank into the *_out arrays, and src.
+void launch_reorder(const DevBufs& d, int s, int buf, PState* st_out, int32_t* sid_out, uint32_t* meta_out,
+                    int32_t* pcell_out, uint32_t* prank_out, hipStream_t st);
 void launch_scan(uint32_t* in_out_cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipStream_t st);
 void launch_scatter(const DevBufs& d, int s, hipStream_t st);
 // Owner-side search at state s; reads list/history parity (l_old, h_old) and
-// writes (1-l_old, 1-h_old).
-void launch_search(const DevBufs& d, int s, int l_old, int h_old, hipStream_t st);
+// writes (1-l_old, 1-h_old).  src: NULL, or (after a re-sort) the index each
+// particle had when the previous lists were built.
+void launch_search(const DevBufs& d, int s, int l_old, int h_old, const int32_t* src, hipStream_t st);
 void launch_rev_scatter(const DevBufs& d, int l, hipStream_t st);
 void launch_rev_sort(const DevBufs& d, hipStream_t st);
 // persist_blocks > 0: persistent grid of that many launch blocks.
@@ -111,6 +135,14 @@ void launch_step(const DevBufs& d, const StepPar& p, int block, int record, int 
 int step_occupancy(int block);
 void launch_advance(const DevBufs& d, int block, hipStream_t st);
 void launch_poses(const DevBufs& d, hipStream_t st);
+// Per-contact loads of the last step for the particles [p0, p0 + np) of one
+// bed: cnt[t] = contacts of particle p0 + t (owner slots in contact and
+// walls), then, with off the exclusive scan of cnt, one record per contact
+// at out[off[t] ...] in slot order, walls last (not yet in canonical order).
+void launch_load_count(const DevBufs& d, int l, int h, int64_t p0, int64_t np, int nwall, uint32_t* cnt,
+                       hipStream_t st);
+void launch_load_pack(const DevBufs& d, int l, int h, int64_t p0, int64_t np, int nwall, const uint32_t* off,
+                      lpr_contact_load* out, hipStream_t st);
 size_t scan_tmp_elems(int64_t n);
 void launch_adj_pre(const DevBufs& d, const AdjBufs& a, int q, hipStream_t st);
 void launch_adj_step(const DevBufs& d, const AdjBufs& a, int q, int hp, int obj_body, float invT, hipStream_t st);

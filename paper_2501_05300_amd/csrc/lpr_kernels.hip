@@ -83,11 +83,23 @@ LPR_DEV_INLINE float ord_val(uint32_t k) {
 // Consecutive particles mostly share cells: the lanes of a wave that fall in
 // one cell take their ranks from a single atomic (ballot, prefix count), and
 // the wave's atomics for all its cells go out in one instruction.
+//
+// SORT also writes the particle's sort key, its level's first cell id plus
+// the Morton rank of its cell in the level grid (so keys order particles by
+// bed, level and Morton code of the cell), and its storage index; padding
+// gets a key above every cell.
+template <bool SORT>
 __global__ void k_bin(DevBufs d, int s) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= d.N || latched(d.err)) return;
   const uint32_t m = d.meta[i];
-  if (m == INACTIVE) return;
+  if (m == INACTIVE) {
+    if (SORT) {
+      d.skey[0][i] = (1u << d.sort_bits) - 1u;
+      d.sval[0][i] = (int32_t)i;
+    }
+    return;
+  }
   const BedConst& bc = d.beds[m >> 8];
   const int gl = bc.lev0 + (int)(m & 0xffu);
   const LevelGrid& G = d.levels[gl];
@@ -95,6 +107,11 @@ __global__ void k_bin(DevBufs d, int s) {
   const int cx = cell_axis(G, 0, p.x), cy = cell_axis(G, 1, p.y), cz = cell_axis(G, 2, p.z);
   const int32_t c = (int32_t)(G.base + ((int64_t)cz * G.n[1] + cy) * G.n[0] + cx);
   d.pcell[i] = c;
+  if (SORT) {
+    const int32_t cc[3] = {cx, cy, cz};
+    d.skey[0][i] = (uint32_t)(G.base + morton_rank(cc, G.n));
+    d.sval[0][i] = (int32_t)i;
+  }
   // group the wave's lanes by cell (votes only), then one atomic per group,
   // all groups' atomics issued together
   const int lane = (int)(threadIdx.x & 63u);
@@ -128,8 +145,9 @@ __global__ void k_bin(DevBufs d, int s) {
   if (klo > *(const volatile uint32_t*)&d.zext[2 * gl + 1]) atomicMax(&d.zext[2 * gl + 1], klo);
 }
 
-void launch_bin(const DevBufs& d, int s, hipStream_t st) {
-  hipLaunchKernelGGL(k_bin, dim3((unsigned)((d.N + 255) / 256)), dim3(256), 0, st, d, s);
+void launch_bin(const DevBufs& d, int s, int sort, hipStream_t st) {
+  if (sort) hipLaunchKernelGGL(k_bin<true>, dim3((unsigned)((d.N + 255) / 256)), dim3(256), 0, st, d, s);
+  else hipLaunchKernelGGL(k_bin<false>, dim3((unsigned)((d.N + 255) / 256)), dim3(256), 0, st, d, s);
 }
 
 // Fills the cell lists, with the position, radius and stable id copied
@@ -236,6 +254,120 @@ void launch_scan(uint32_t* cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipSt
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SB), 0, st, cnt, tmp, n);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SB), 0, st, tmp, tiles);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(SB), 0, st, cnt, start, tmp, n);
+}
+
+// ---------------------------------------------------------------------------
+// storage-order sort: stable LSD radix sort of 32-bit keys, 8-bit digits
+//
+// Each pass: every tile of RS_TILE consecutive entries counts its digits
+// (k_rs_hist, digit-major table), the table is scanned (digit d of tile t
+// starts after every smaller digit and after digit d of earlier tiles), and
+// k_rs_scatter moves each entry to its place.  Within a tile the entries are
+// taken in order, a wave at a time: the lanes holding one digit are found by
+// eight ballots, a lane's rank among them is the count of lower lanes, the
+// lowest lane records the group's size, and one thread per digit turns the
+// waves' sizes into offsets.  Equal keys keep their order, so the sorted
+// order is (key, previous storage index) whatever the scheduling.
+
+constexpr int RS_BS = 256, RS_ROUNDS = 8, RS_TILE = RS_BS * RS_ROUNDS, RS_BINS = 256;
+static_assert(RS_BS == RS_BINS, "one thread per digit");
+
+__global__ __launch_bounds__(RS_BS) void k_rs_hist(const uint32_t* __restrict__ key, int64_t n, int shift,
+                                                 uint32_t* __restrict__ hist, int64_t ntiles) {
+  __shared__ uint32_t h[RS_BINS];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t base = blockIdx.x * (int64_t)RS_TILE;
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int64_t q = base + r * RS_BS + threadIdx.x;
+    if (q < n) atomicAdd(&h[(key[q] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RS_BS) void k_rs_scatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
+                                                    uint32_t* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
+                                                    int shift, const uint32_t* __restrict__ hoff, int64_t ntiles) {
+  __shared__ uint32_t wofs[RS_BS / 64][RS_BINS];  // per wave: group size, then the group's first position
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int dig = threadIdx.x;                    // the digit this thread keeps the running position of
+  uint32_t run = hoff[(int64_t)dig * ntiles + blockIdx.x];
+  const int64_t base = blockIdx.x * (int64_t)RS_TILE;
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+#pragma unroll
+    for (int w = 0; w < RS_BS / 64; ++w) wofs[w][dig] = 0u;
+    __syncthreads();
+    const int64_t q = base + r * RS_BS + threadIdx.x;
+    const bool ok = q < n;
+    const uint32_t k = ok ? kin[q] : 0u;
+    const int32_t v = ok ? vin[q] : 0;
+    const uint32_t dg = (k >> shift) & 255u;
+    uint64_t same = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t set = __ballot((dg >> b) & 1u);
+      same &= ((dg >> b) & 1u) ? set : ~set;
+    }
+    const uint32_t rk = (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+    if (ok && rk == 0u) wofs[wv][dg] = (uint32_t)__popcll(same);
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < RS_BS / 64; ++w) {
+      const uint32_t c = wofs[w][dig];
+      wofs[w][dig] = run;
+      run += c;
+    }
+    __syncthreads();
+    if (ok) {
+      const uint32_t at = wofs[wv][dg] + rk;
+      kout[at] = k;
+      vout[at] = v;
+    }
+    __syncthreads();
+  }
+}
+
+size_t sort_hist_elems(int64_t n) { return (size_t)RS_BINS * (size_t)((n + RS_TILE - 1) / RS_TILE) + 1; }
+
+int launch_sort(const DevBufs& d, hipStream_t st) {
+  const int64_t n = d.N, ntiles = (n + RS_TILE - 1) / RS_TILE;
+  const int passes = (d.sort_bits + 7) / 8;
+  for (int p = 0; p < passes; ++p) {
+    const int a = p & 1;
+    hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(RS_BS), 0, st, d.skey[a], n, 8 * p, d.rs_hist, ntiles);
+    launch_scan(d.rs_hist, d.rs_hist, d.scan_tmp, RS_BINS * ntiles, st);
+    hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(RS_BS), 0, st, d.skey[a], d.sval[a], d.skey[a ^ 1],
+                       d.sval[a ^ 1], n, 8 * p, d.rs_hist, ntiles);
+  }
+  return passes;
+}
+
+// Sorted rank r holds a particle of some bed; its new storage index is r plus
+// that bed's offset (beds keep their padded ranges, their particles come
+// first in them).  Reads are gathers, writes are in storage order.
+__global__ void k_reorder(DevBufs d, int s, int buf, PState* __restrict__ st_out, int32_t* __restrict__ sid_out,
+                          uint32_t* __restrict__ meta_out, int32_t* __restrict__ pcell_out,
+                          uint32_t* __restrict__ prank_out) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= d.n_active || latched(d.err)) return;
+  const int32_t o = d.sval[buf][r];
+  const uint32_t m = d.meta[o];
+  const int64_t i = r + d.beds[m >> 8].sort_off;
+  st_out[i] = d.st[s][o];
+  sid_out[i] = d.sid[o];
+  meta_out[i] = m;
+  pcell_out[i] = d.pcell[o];
+  prank_out[i] = d.prank[o];
+  d.src[i] = o;
+}
+
+void launch_reorder(const DevBufs& d, int s, int buf, PState* st_out, int32_t* sid_out, uint32_t* meta_out,
+                    int32_t* pcell_out, uint32_t* prank_out, hipStream_t st) {
+  if (d.n_active <= 0) return;
+  hipLaunchKernelGGL(k_reorder, dim3((unsigned)((d.n_active + 255) / 256)), dim3(256), 0, st, d, s, buf, st_out,
+                     sid_out, meta_out, pcell_out, prank_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -485,7 +617,10 @@ LPR_DEV_INLINE bool owner_candidate(const BedConst& bc, const double4& pi, int32
 
 // Five waves per SIMD: 8 KB of LDS per 64-lane block and at most 96 VGPRs
 // (the previous lists' partners are read after the walk to stay within them).
-__global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k_search(DevBufs d, int s, int lo, int ho) {
+// src (after a re-sort of the storage order): the index each particle had
+// when the previous lists were built; their partners are matched through it.
+__global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k_search(DevBufs d, int s, int lo, int ho,
+                                                                                       const int32_t* __restrict__ src) {
   // rows of the level being walked are packed as (first cell-list position
   // << 6 | length); the rows' layout over the array is described at LROWS
   __shared__ int32_t lds[LROWS][SBS];
@@ -516,8 +651,9 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
   const double4 pi = d.st[s][i].x;
   // the previous lists' flags and count, read now so that their latency
   // hides behind the walk
-  const uint32_t fo = d.cflag[ho][i];
-  const int cnt_old = d.own_cnt[lo][i];
+  const int64_t io = src ? (int64_t)src[i] : i;
+  const uint32_t fo = d.cflag[ho][io];
+  const int cnt_old = d.own_cnt[lo][io];
   const float rif = (float)pi.w;
   const int32_t si = d.sid[i];
   const double skin = (double)bc.skin;
@@ -593,7 +729,7 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
   // the previous lists' partners, read alongside the exact pass
   int32_t old_j[K];
 #pragma unroll
-  for (int k2 = 0; k2 < K; ++k2) old_j[k2] = (k2 < cnt_old) ? d.own_idx[lo][k2 * N + i] : -1;
+  for (int k2 = 0; k2 < K; ++k2) old_j[k2] = (k2 < cnt_old) ? d.own_idx[lo][k2 * N + io] : -1;
   // exact pass over the kept candidates, reads four at a time; accepted ones
   // are compacted in place
   int cnt = 0;
@@ -646,13 +782,16 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
     uint32_t rk[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) rk[u] = (k0 + u < cnt) ? atomicAdd(&d.rev_cnt[jj[u]], 1u) : 0u;
+    int32_t jo[4];  // the partner's index in the previous lists
+#pragma unroll
+    for (int u = 0; u < 4; ++u) jo[u] = (src && k0 + u < cnt) ? src[jj[u]] : jj[u];
     int mk[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       mk[u] = -1;
 #pragma unroll
       for (int k2 = K - 1; k2 >= 0; --k2)
-        if (old_j[k2] == jj[u]) mk[u] = k2;
+        if (old_j[k2] == jo[u]) mk[u] = k2;
     }
     HRec hr[4];
 #pragma unroll
@@ -660,7 +799,7 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
       hr[u].t = make_float4(0.f, 0.f, 0.f, 0.f);
       hr[u].r = make_float4(0.f, 0.f, 0.f, 0.f);
       if (mk[u] >= 0 && ((fo >> mk[u]) & 1u)) {
-        hr[u] = d.hist[ho][(int64_t)mk[u] * N + i];
+        hr[u] = d.hist[ho][(int64_t)mk[u] * N + io];
         fn |= 1u << (k0 + u);
       }
     }
@@ -675,8 +814,8 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
   }
   for (int w = 0; w < bc.nwall; ++w)
     if ((fo >> (WALL_BIT + w)) & 1u) {
-      d.wA[hn][w * N + i] = d.wA[ho][w * N + i];
-      d.wB[hn][w * N + i] = d.wB[ho][w * N + i];
+      d.wA[hn][w * N + i] = d.wA[ho][w * N + io];
+      d.wB[hn][w * N + i] = d.wB[ho][w * N + io];
     }
   d.own_cnt[ln][i] = cnt;
   d.cflag[hn][i] = fn;
@@ -685,9 +824,9 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
   if ((uint32_t)cnt > *(const volatile uint32_t*)&d.stat[0]) atomicMax(&d.stat[0], (uint32_t)cnt);
 }
 
-void launch_search(const DevBufs& d, int s, int lo, int ho, hipStream_t st) {
+void launch_search(const DevBufs& d, int s, int lo, int ho, const int32_t* src, hipStream_t st) {
   const int64_t g = (d.N + SBS - 1) / SBS;
-  hipLaunchKernelGGL(k_search, dim3((unsigned)((g + 7) / 8 * 8)), dim3(SBS), 0, st, d, s, lo, ho);
+  hipLaunchKernelGGL(k_search, dim3((unsigned)((g + 7) / 8 * 8)), dim3(SBS), 0, st, d, s, lo, ho, src);
 }
 
 __global__ void k_rev_scatter(DevBufs d, int l) {
@@ -907,6 +1046,10 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
         hr.r = make_float4(out.xr.x, out.xr.y, out.xr.z, 0.f);
         d.hist[hn][k * N + i] = hr;
         fnew |= 1u << k;
+        if (record) {
+          d.cF[k * N + i] = make_float4(out.F.x, out.F.y, out.F.z, out.Fn);
+          d.cM[k * N + i] = make_float4(out.M.x, out.M.y, out.M.z, 0.f);
+        }
       } else {
         F = F - out.F;
         T = T + (lb * nft - out.M);
@@ -957,6 +1100,10 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
         d.wA[hn][w * N + i] = make_float4(out.xt.x, out.xt.y, out.xt.z, out.xr.x);
         d.wB[hn][w * N + i] = make_float2(out.xr.y, out.xr.z);
         fnew |= 1u << (WALL_BIT + w);
+        if (record) {
+          d.wF[w * N + i] = make_float4(out.F.x, out.F.y, out.F.z, out.Fn);
+          d.wM[w * N + i] = make_float4(out.M.x, out.M.y, out.M.z, 0.f);
+        }
         // reaction on the body: -F at p, and -M
         const double fx = -(double)out.F.x, fy = -(double)out.F.y, fz = -(double)out.F.z;
         r6[0] += fx; r6[1] += fy; r6[2] += fz;
@@ -1199,6 +1346,75 @@ __global__ void k_poses(DevBufs d) {
 
 void launch_poses(const DevBufs& d, hipStream_t st) {
   hipLaunchKernelGGL(k_poses, dim3((unsigned)d.nbeds), dim3(64), 0, st, d);
+}
+
+// ---------------------------------------------------------------------------
+// per-contact loads of the last step, compacted on the device
+
+LPR_DEV_INLINE uint32_t contact_bits(const DevBufs& d, int l, int h, int64_t i, int nwall) {
+  const uint32_t fl = d.cflag[h][i];
+  const int own = d.own_cnt[l][i];
+  const uint32_t slots = fl & ((1u << own) - 1u) & 0xffffu;
+  const uint32_t walls = (fl >> WALL_BIT) & ((1u << nwall) - 1u);
+  return slots | (walls << WALL_BIT);
+}
+
+__global__ void k_load_count(DevBufs d, int l, int h, int64_t p0, int64_t np, int nwall, uint32_t* cnt) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= np) return;
+  const int64_t i = p0 + t;
+  cnt[t] = (d.sid[i] < 0) ? 0u : (uint32_t)__popc(contact_bits(d, l, h, i, nwall));
+}
+
+__global__ void k_load_pack(DevBufs d, int l, int h, int64_t p0, int64_t np, int nwall, const uint32_t* off,
+                            lpr_contact_load* out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= np) return;
+  const int64_t i = p0 + t, N = d.N;
+  const int32_t a = d.sid[i];
+  if (a < 0) return;
+  uint32_t q = off[t];
+  const uint32_t bits = contact_bits(d, l, h, i, nwall);
+  for (int k = 0; k < K; ++k) {
+    if (!((bits >> k) & 1u)) continue;
+    const int32_t b = d.sid[d.own_idx[l][(int64_t)k * N + i]];
+    const float4 F = d.cF[(int64_t)k * N + i], M = d.cM[(int64_t)k * N + i];
+    // loads are kept for the owner; a pair is reported on its smaller id
+    const float sg = (a < b) ? 1.f : -1.f;
+    lpr_contact_load r;
+    r.a = (a < b) ? a : b;
+    r.b = (a < b) ? b : a;
+    r.force[0] = sg * F.x; r.force[1] = sg * F.y; r.force[2] = sg * F.z;
+    r.moment[0] = sg * M.x; r.moment[1] = sg * M.y; r.moment[2] = sg * M.z;
+    r.fn = F.w;
+    r.reserved = 0.f;
+    out[q++] = r;
+  }
+  for (int w = 0; w < nwall; ++w) {
+    if (!((bits >> (WALL_BIT + w)) & 1u)) continue;
+    const float4 F = d.wF[(int64_t)w * N + i], M = d.wM[(int64_t)w * N + i];
+    lpr_contact_load r;
+    r.a = a;
+    r.b = -1 - (int64_t)w;
+    r.force[0] = F.x; r.force[1] = F.y; r.force[2] = F.z;
+    r.moment[0] = M.x; r.moment[1] = M.y; r.moment[2] = M.z;
+    r.fn = F.w;
+    r.reserved = 0.f;
+    out[q++] = r;
+  }
+}
+
+void launch_load_count(const DevBufs& d, int l, int h, int64_t p0, int64_t np, int nwall, uint32_t* cnt,
+                       hipStream_t st) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_load_count, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, d, l, h, p0, np, nwall, cnt);
+}
+
+void launch_load_pack(const DevBufs& d, int l, int h, int64_t p0, int64_t np, int nwall, const uint32_t* off,
+                      lpr_contact_load* out, hipStream_t st) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_load_pack, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, d, l, h, p0, np, nwall, off,
+                     out);
 }
 
 }  // namespace lpr

@@ -40,8 +40,8 @@ struct HostBed {
   int64_t n = 0;       // particles
   int64_t p0 = 0;      // first storage index
   int64_t npad = 0;    // padded count
-  std::vector<int64_t> perm;  // storage offset -> stable id
-  std::vector<int64_t> inv;   // stable id -> storage offset
+  std::vector<int64_t> perm;  // storage offset -> stable id at creation (a re-sort changes it; the
+                              // device's sid array is the current map)
   int nwall = 0, nbody = 0, nlev = 0;
   int wall0 = 0, body0 = 0, lev0 = 0;
   double dt = 0.0;
@@ -87,10 +87,12 @@ bool finite_arrf(const float* a, int64_t n) {
 
 }  // namespace
 
-// Host view of the buffer parities (state, history, lists) and the steps
-// since the last broad-phase rebuild.
+// Host view of the buffer parities (state, history, lists, storage order)
+// and the steps since the last broad-phase rebuild.
 struct Par {
   int s = 0, h = 0, l = 0;
+  int o = 0;   // storage order: flips at each re-sort
+  int sc = 0;  // rebuilds since the last re-sort, modulo the sort cadence
   int64_t since = std::numeric_limits<int64_t>::max() / 2;
 };
 
@@ -108,6 +110,24 @@ struct lpr_bed {
   int R = 1;      // configured rebuild cadence
   int R_eff = 1;  // cadence in use (halved after a skin trip, restored per lpr_step)
   float skin = 0.f;
+  // storage-order sort: every sort_every-th rebuild (0: never) re-sorts the
+  // particles by (bed, level, Morton code of the cell); the sorted copies go
+  // to the second buffer of each pair below and the pairs swap (order parity o)
+  int sort_every = 0;
+  bool sort_hold = false;  // suspended (adjoint windows keep one order)
+  int o = 0, sc = 0;
+  int64_t sorts = 0;
+  int32_t* sid_alt = nullptr;
+  uint32_t* meta_alt = nullptr;
+  int32_t* pcell_alt = nullptr;
+  uint32_t* prank_alt = nullptr;
+  int go = 0;  // order parity the captured cycle starts from
+  // phase timing: when set, the enqueue functions record these events at the
+  // phase boundaries of the step being enqueued (see lpr_step_phases)
+  hipEvent_t* pev = nullptr;
+  int device = 0;                 // the GPU the bed lives on
+  char* ld_ws = nullptr;          // workspace of the per-contact read (grown on demand)
+  size_t ld_ws_bytes = 0;
   // host parities
   int s = 0, h = 0, l = 0;
   int64_t since = std::numeric_limits<int64_t>::max() / 2;  // steps since the last rebuild
@@ -162,6 +182,16 @@ struct lpr_bed {
     if (p) blocks.push_back(p);
     return p;
   }
+  void dfree(void* p) {
+    if (!p) return;
+    for (size_t q = 0; q < blocks.size(); ++q)
+      if (blocks[q] == p) {
+        blocks.erase(blocks.begin() + (long)q);
+        break;
+      }
+    if (use_hip_malloc) (void)hipFree(p);
+    else alloc.release(alloc.ctx, p);
+  }
   void release_all() {
     for (void* p : blocks) {
       if (use_hip_malloc) (void)hipFree(p);
@@ -213,6 +243,7 @@ lpr_status validate(const lpr_bed_desc* d) {
   if (d->cell_factor != 0.f && !(d->cell_factor >= 1.f)) return fail(LPR_E_INVAL, "cell_factor must be >= 1");
   if (d->block != 0 && d->block != 64 && d->block != 128 && d->block != 256)
     return fail(LPR_E_INVAL, "block must be 64, 128 or 256");
+  if (d->sort_every > 4096) return fail(LPR_E_INVAL, "sort_every must be at most 4096");
   float rmax = 0.f;
   for (int64_t i = 0; i < d->n; ++i) rmax = std::max(rmax, d->radius[i]);
   for (int a = 0; a < 2; ++a)
@@ -223,7 +254,7 @@ lpr_status validate(const lpr_bed_desc* d) {
 }
 
 // Builds radius bands, level grids and the Morton storage order of one bed.
-void plan_bed(const lpr_bed_desc* D, double band_ratio, double cell_factor, double skin, HostBed& H,
+void plan_bed(const lpr_bed_desc* D, double band_ratio, double cell_factor, double skin, bool input_order, HostBed& H,
               std::vector<LevelGrid>& levels, int64_t& cell_base, std::vector<uint8_t>& lev_of) {
   const int64_t n = D->n;
   double rlo = std::numeric_limits<double>::max();
@@ -287,7 +318,11 @@ void plan_bed(const lpr_bed_desc* D, double band_ratio, double cell_factor, doub
     cell_base += (int64_t)G.n[0] * G.n[1] * G.n[2];
     levels.push_back(G);
   }
-  // storage order: level, then Morton code of the cell, then stable id
+  // storage order: level, then Morton code of the cell, then stable id (the
+  // order a device re-sort keeps); or the caller's order
+  H.perm.resize(n);
+  for (int64_t i = 0; i < n; ++i) H.perm[i] = i;
+  if (input_order) return;
   std::vector<uint64_t> key(n);
   for (int64_t i = 0; i < n; ++i) {
     const LevelGrid& G = levels[H.lev0 + lev_of[i]];
@@ -296,33 +331,47 @@ void plan_bed(const lpr_bed_desc* D, double band_ratio, double cell_factor, doub
     const uint64_t cz = (uint64_t)host_cell_axis(G, 2, D->pos[3 * i + 2]);
     key[i] = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
   }
-  H.perm.resize(n);
-  for (int64_t i = 0; i < n; ++i) H.perm[i] = i;
   std::sort(H.perm.begin(), H.perm.end(), [&](int64_t a, int64_t b) {
     if (lev_of[a] != lev_of[b]) return lev_of[a] < lev_of[b];
     if (key[a] != key[b]) return key[a] < key[b];
     return a < b;
   });
-  H.inv.resize(n);
-  for (int64_t i = 0; i < n; ++i) H.inv[H.perm[i]] = i;
 }
 
 Par cur_par(const lpr_bed* b) {
   Par p;
-  p.s = b->s; p.h = b->h; p.l = b->l; p.since = b->since;
+  p.s = b->s; p.h = b->h; p.l = b->l; p.o = b->o; p.sc = b->sc; p.since = b->since;
   return p;
 }
 
-void set_par(lpr_bed* b, const Par& p) {
-  b->s = p.s; b->h = p.h; b->l = p.l; b->since = p.since;
+// Swaps every buffer pair that a re-sort writes: the state pair (the sorted
+// state goes to the buffer the next step would write), stable ids, metadata,
+// cells and cell ranks.
+void swap_order(lpr_bed* b) {
+  std::swap(b->d.st[0], b->d.st[1]);
+  std::swap(b->d.sid, b->sid_alt);
+  std::swap(b->d.meta, b->meta_alt);
+  std::swap(b->d.pcell, b->pcell_alt);
+  std::swap(b->d.prank, b->prank_alt);
+  b->o ^= 1;
 }
 
-// Parity changes of one step, as enqueue_step makes them.
-void simulate_step(Par& p, int R) {  // R: the cadence of the captured cycle
+void set_par(lpr_bed* b, const Par& p) {
+  if (p.o != b->o) swap_order(b);
+  b->s = p.s; b->h = p.h; b->l = p.l; b->sc = p.sc; b->since = p.since;
+}
+
+// Parity changes of one step, as enqueue_step makes them (R: the cadence of
+// the captured cycle, S: rebuilds per re-sort, 0 for none).
+void simulate_step(Par& p, int R, int S) {
   if (p.since >= R) {
     p.l ^= 1;
     p.h ^= 1;
     p.since = 0;
+    if (S > 0) {
+      if (p.sc == 0) p.o ^= 1;
+      p.sc = (p.sc + 1) % S;
+    }
   }
   p.s ^= 1;
   p.h ^= 1;
@@ -369,6 +418,13 @@ lpr_status sync_check(lpr_bed* b) {
   uint32_t e = 0;
   HIPTRY(hipMemcpy(&e, b->d.err, sizeof(uint32_t), hipMemcpyDeviceToHost));
   {
+    // the device stopped at the last complete step: take the host view of
+    // the buffers back to it (a re-sort enqueued after that step wrote only
+    // the second buffers, so the state and ids of that step are intact)
+    BedDyn bd;
+    HIPTRY(hipMemcpy(&bd, b->d.bedyn, sizeof(BedDyn), hipMemcpyDeviceToHost));
+    const int64_t done = bd.completed - b->base_steps;
+    if (done >= 0 && done <= (int64_t)b->plog.size()) set_par(b, done == 0 ? b->base_par : b->plog[(size_t)(done - 1)]);
     b->faulted = true;
     if (e & ERR_CAPACITY) b->fault_status = LPR_E_CAPACITY;
     else if (e & ERR_NUMERIC) b->fault_status = LPR_E_NUMERIC;
@@ -380,19 +436,37 @@ lpr_status sync_check(lpr_bed* b) {
   return LPR_OK;
 }
 
+void mark(lpr_bed* b, int k) {
+  if (b->pev) (void)hipEventRecord(b->pev[k], b->stream);
+}
+
 void enqueue_rebuild(lpr_bed* b) {
   DevBufs& d = b->d;
+  const bool srt = b->sort_every > 0 && !b->sort_hold && b->sc == 0;
   launch_zero(d.cell_cnt, d.ncells, b->stream);
   launch_zero(d.rev_cnt, d.N, b->stream);
-  launch_bin(d, b->s, b->stream);
+  launch_bin(d, b->s, srt ? 1 : 0, b->stream);
   launch_scan(d.cell_cnt, d.cell_start, d.scan_tmp, d.ncells, b->stream);
+  mark(b, 1);
+  if (srt) {
+    const int passes = launch_sort(d, b->stream);
+    launch_reorder(d, b->s, passes & 1, d.st[b->s ^ 1], b->sid_alt, b->meta_alt, b->pcell_alt, b->prank_alt,
+                   b->stream);
+    swap_order(b);
+    b->sorts += 1;
+  }
+  if (b->sort_every > 0 && !b->sort_hold) b->sc = (b->sc + 1) % b->sort_every;
+  mark(b, 2);
   launch_scatter(d, b->s, b->stream);
-  launch_search(d, b->s, b->l, b->h, b->stream);
+  mark(b, 3);
+  launch_search(d, b->s, b->l, b->h, srt ? d.src : nullptr, b->stream);
+  mark(b, 4);
   b->l ^= 1;
   b->h ^= 1;
   launch_scan(d.rev_cnt, d.rev_start, d.scan_tmp, d.N, b->stream);
   launch_rev_scatter(d, b->l, b->stream);
   launch_rev_sort(d, b->stream);
+  mark(b, 5);
   b->since = 0;
   b->rebuilds += 1;
 }
@@ -428,10 +502,16 @@ void enqueue_step(lpr_bed* b) {
   b->plog.push_back(cur_par(b));
 }
 
+// Steps of the captured cycle: two re-sorts' worth of rebuilds (two
+// rebuilds without sorting), so that every buffer pair is back where it
+// started at the end of the cycle.
+int cycle_steps(const lpr_bed* b) { return 2 * b->R * (b->sort_every > 0 ? b->sort_every : 1); }
+
 lpr_status capture_cycle(lpr_bed* b) {
-  const int S = 2 * b->R;
-  const int s0 = b->s, h0 = b->h, l0 = b->l;
-  const int64_t since0 = b->since, steps0 = b->host_steps, reb0 = b->rebuilds;
+  const int S = cycle_steps(b);
+  const Par p0 = cur_par(b);
+  const int s0 = b->s, h0 = b->h, l0 = b->l, o0 = b->o;
+  const int64_t since0 = b->since, steps0 = b->host_steps, reb0 = b->rebuilds, sorts0 = b->sorts;
   const size_t plog0 = b->plog.size();
   HIPTRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
   for (int q = 0; q < S; ++q) enqueue_step(b);
@@ -441,13 +521,14 @@ lpr_status capture_cycle(lpr_bed* b) {
   HIPTRY(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
   b->graph = g;
   b->gexec = ex;
-  b->gs = s0; b->gh = h0; b->gl = l0;
+  b->gs = s0; b->gh = h0; b->gl = l0; b->go = o0;
   b->gsteps = S;
   b->has_graph = true;
   // the capture only recorded; restore the host view
-  b->s = s0; b->h = h0; b->l = l0;
-  b->since = since0; b->host_steps = steps0; b->rebuilds = reb0;
+  set_par(b, p0);
+  b->host_steps = steps0; b->rebuilds = reb0; b->sorts = sorts0;
   b->plog.resize(plog0);
+  (void)since0;
   return LPR_OK;
 }
 
@@ -499,6 +580,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
     }
     b->own_stream = true;
   }
+  (void)hipGetDevice(&b->device);
   b->block = D0.block ? D0.block : 256;
   if (D0.persistent) {
     int dev = 0, cus = 0;
@@ -510,6 +592,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   b->R = std::max(1, D0.rebuild_every);
   b->R_eff = b->R;
   b->skin = b->R > 1 ? D0.skin : 0.f;
+  b->sort_every = D0.sort_every < 0 ? 0 : (D0.sort_every > 0 ? D0.sort_every : (b->R == 1 ? 16 : 1));
 
   // plan beds
   std::vector<LevelGrid> levels;
@@ -526,7 +609,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
     p += H.npad;
     const double band = D->band_ratio > 0.f ? D->band_ratio : 2.0;
     const double cfac = D->cell_factor > 0.f ? D->cell_factor : 1.0;
-    plan_bed(D, band, cfac, (double)b->skin, H, levels, cell_base, lev_of[q]);
+    plan_bed(D, band, cfac, (double)b->skin, D0.input_order != 0, H, levels, cell_base, lev_of[q]);
     H.nwall = D->n_walls;
     H.nbody = std::max(1, D->n_bodies);
     H.wall0 = wall_total;
@@ -541,8 +624,14 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
     for (int64_t i = 0; i < D->n; ++i) H.rmin = std::min(H.rmin, (double)D->radius[i]);
   }
   if (cell_base >= (int64_t(1) << 31) - 2) {
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return fail(LPR_E_INVAL, "too many cells; raise cell_factor");
+  }
+  if (p >= (int64_t(1) << 27)) {
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return fail(LPR_E_INVAL, "too many particles for packed contact entries (padded total >= 2^27)");
   }
   b->nlev_total = (int)levels.size();
   b->ncells = cell_base;
@@ -567,7 +656,21 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   ok &= dal(b, &d.disp, N) && dal(b, &d.viol, 2);
   ok &= dal(b, &d.own_rank, (size_t)K * N) && dal(b, &d.rev_cnt, N) && dal(b, &d.rev_start, N + 1);
   ok &= dal(b, &d.rev_ent, (size_t)K * N);
-  if (b->record) ok &= dal(b, &d.frc, N) && dal(b, &d.trq, N);
+  if (b->record) {
+    ok &= dal(b, &d.frc, N) && dal(b, &d.trq, N);
+    ok &= dal(b, &d.cF, (size_t)K * N) && dal(b, &d.cM, (size_t)K * N);
+    ok &= dal(b, &d.wF, (size_t)max_walls * N) && dal(b, &d.wM, (size_t)max_walls * N);
+  }
+  d.nwall_max = max_walls;
+  if (b->sort_every > 0) {
+    for (int q = 0; q < 2; ++q) ok &= dal(b, &d.skey[q], N) && dal(b, &d.sval[q], N);
+    ok &= dal(b, &d.rs_hist, sort_hist_elems(N)) && dal(b, &d.src, N);
+    ok &= dal(b, &b->sid_alt, N) && dal(b, &b->meta_alt, N) && dal(b, &b->pcell_alt, N) && dal(b, &b->prank_alt, N);
+  }
+  d.sort_bits = 1;
+  while ((int64_t(1) << d.sort_bits) <= cell_base) ++d.sort_bits;
+  d.n_active = 0;
+  for (const HostBed& H : b->hb) d.n_active += H.n;
   d.nblk = N / 64;
   ok &= dal(b, &d.partial, (size_t)d.nblk * 6 * std::max(1, body_total));
   ok &= dal(b, &d.scan_tmp, std::max(scan_tmp_elems(cell_base), scan_tmp_elems(N + 1)));
@@ -640,6 +743,11 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
     C.dt_d = P.dt;
     for (int a = 0; a < 3; ++a) C.g[a] = (float)P.g[a];
     C.law = (P.e_H == 1.25) ? 0 : (P.e_H == 1.0 ? 1 : 2);
+    {
+      int64_t before = 0;  // particles of the beds before this one
+      for (int q2 = 0; q2 < q; ++q2) before += b->hb[q2].n;
+      C.sort_off = (int32_t)(H.p0 - before);
+    }
     for (int w = 0; w < H.nwall; ++w) {
       const lpr_wall& W = D->walls[w];
       WallDef& X = hwd[H.wall0 + w];
@@ -684,6 +792,10 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   e = (hipError_t)(e | up(d.st[1], hst.data(), sizeof(PState) * N));
   e = (hipError_t)(e | up(d.sid, hsid.data(), sizeof(int32_t) * N));
   e = (hipError_t)(e | up(d.meta, hmeta.data(), sizeof(uint32_t) * N));
+  if (b->sort_every > 0) {  // padding keeps its marks in both buffers of each pair
+    e = (hipError_t)(e | up(b->sid_alt, hsid.data(), sizeof(int32_t) * N));
+    e = (hipError_t)(e | up(b->meta_alt, hmeta.data(), sizeof(uint32_t) * N));
+  }
   e = (hipError_t)(e | up(d.chunk_bed32, hchunk.data(), sizeof(int32_t) * (N / PAD)));
   e = (hipError_t)(e | up(d.beds, hbc.data(), sizeof(BedConst) * nb));
   e = (hipError_t)(e | up(d.levels, levels.data(), sizeof(LevelGrid) * levels.size()));
@@ -758,23 +870,26 @@ lpr_status lpr_step(lpr_bed* b, int64_t n_steps) {
   if (n_steps < 0) return fail(LPR_E_INVAL, "n_steps must be >= 0");
   b->R_eff = b->R;
   while (n_steps > 0) {
-    const bool at_cycle = (b->since >= b->R);
-    if (at_cycle && n_steps >= 2 * b->R) {
+    const bool at_cycle = (b->since >= b->R) && (b->sort_every <= 0 || b->sc == 0);
+    if (at_cycle && n_steps >= cycle_steps(b)) {
       if (!b->has_graph) {
         lpr_status st = capture_cycle(b);
         if (st != LPR_OK) return st;
       }
-      if (b->s == b->gs && b->h == b->gh && b->l == b->gl) {
+      if (b->s == b->gs && b->h == b->gh && b->l == b->gl && b->o == b->go) {
         HIPTRY(hipGraphLaunch(b->gexec, b->stream));
-        // a cycle flips s twice, h 2R+2 times, l twice: parities unchanged
+        // a cycle has an even number of steps and of rebuilds and two
+        // re-sorts (or none): every parity is back where it started
         Par p = cur_par(b);
+        const int S = b->sort_every > 0 ? b->sort_every : 0;
         for (int q = 0; q < b->gsteps; ++q) {
-          simulate_step(p, b->R);
+          simulate_step(p, b->R, S);
           b->plog.push_back(p);
         }
         b->since = b->R;
         b->host_steps += b->gsteps;
-        b->rebuilds += 2;
+        b->rebuilds += b->gsteps / b->R;
+        if (S > 0) b->sorts += 2;
         n_steps -= b->gsteps;
         continue;
       }
@@ -822,6 +937,48 @@ lpr_status lpr_step_profiled(lpr_bed* b, int64_t n_steps, double out[4]) {
   return sync_check(b);
 }
 
+lpr_status lpr_step_phases(lpr_bed* b, int64_t n_steps, double out[8]) {
+  lpr_status g = guard(b);
+  if (g != LPR_OK) return g;
+  if (n_steps < 0 || !out) return fail(LPR_E_INVAL, "bad arguments");
+  for (int c = 0; c < 8; ++c) out[c] = 0.0;
+  if (n_steps == 0) return LPR_OK;
+  std::vector<hipEvent_t> ev((size_t)n_steps * 8);
+  for (auto& e : ev) HIPTRY(hipEventCreate(&e));
+  for (int64_t q = 0; q < n_steps; ++q) {
+    b->pev = &ev[8 * q];
+    mark(b, 0);
+    if (b->since >= b->R_eff) {
+      enqueue_rebuild(b);
+    } else {
+      for (int k = 1; k <= 5; ++k) mark(b, k);
+    }
+    const int pb = enqueue_contact_step(b, b->stream);
+    mark(b, 6);
+    launch_advance(b->d, pb, b->stream);
+    mark(b, 7);
+    b->pev = nullptr;
+    b->s ^= 1;
+    b->h ^= 1;
+    b->since += 1;
+    b->host_steps += 1;
+    b->plog.push_back(cur_par(b));
+  }
+  HIPTRY(hipGetLastError());
+  HIPTRY(hipStreamSynchronize(b->stream));
+  for (int64_t q = 0; q < n_steps; ++q)
+    for (int c = 0; c < 7; ++c) {
+      float ms = 0.f;
+      HIPTRY(hipEventElapsedTime(&ms, ev[8 * q + c], ev[8 * q + c + 1]));
+      out[c] += ms;
+    }
+  float tot = 0.f;
+  HIPTRY(hipEventElapsedTime(&tot, ev[0], ev[8 * (n_steps - 1) + 7]));
+  out[7] = tot;
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return sync_check(b);
+}
+
 lpr_status lpr_sync(lpr_bed* b) {
   if (!b) return fail(LPR_E_INVAL, "null bed");
   if (b->faulted) return fail(b->fault_status, "latched device fault");
@@ -835,9 +992,12 @@ static lpr_status get_state_impl(lpr_bed* b, int32_t bed, double* pos, float* ve
   if (st != LPR_OK) return st;
   const HostBed& H = b->hb[bed];
   std::vector<PState> hs(H.npad);
+  std::vector<int32_t> sid(H.npad);
   HIPTRY(hipMemcpy(hs.data(), b->d.st[par] + H.p0, sizeof(PState) * H.npad, hipMemcpyDeviceToHost));
-  for (int64_t off = 0; off < H.n; ++off) {
-    const int64_t q = H.perm[off];
+  HIPTRY(hipMemcpy(sid.data(), b->d.sid + H.p0, sizeof(int32_t) * H.npad, hipMemcpyDeviceToHost));
+  for (int64_t off = 0; off < H.npad; ++off) {
+    if (sid[off] < 0) continue;
+    const int64_t q = sid[off];
     const PState& p = hs[off];
     if (pos) { pos[3 * q] = p.x.x; pos[3 * q + 1] = p.x.y; pos[3 * q + 2] = p.x.z; }
     if (vel) { vel[3 * q] = p.v.x; vel[3 * q + 1] = p.v.y; vel[3 * q + 2] = p.v.z; }
@@ -857,9 +1017,12 @@ static lpr_status set_state_impl(lpr_bed* b, int32_t bed, const double* pos, con
   lpr_status st = state_parity(b, &par);
   if (st != LPR_OK) return st;
   std::vector<PState> hs(H.npad);
+  std::vector<int32_t> sid(H.npad);
   HIPTRY(hipMemcpy(hs.data(), b->d.st[par] + H.p0, sizeof(PState) * H.npad, hipMemcpyDeviceToHost));
-  for (int64_t off = 0; off < H.n; ++off) {
-    const int64_t q = H.perm[off];
+  HIPTRY(hipMemcpy(sid.data(), b->d.sid + H.p0, sizeof(int32_t) * H.npad, hipMemcpyDeviceToHost));
+  for (int64_t off = 0; off < H.npad; ++off) {
+    if (sid[off] < 0) continue;
+    const int64_t q = sid[off];
     PState& p = hs[off];
     if (pos) { p.x.x = pos[3 * q]; p.x.y = pos[3 * q + 1]; p.x.z = pos[3 * q + 2]; }
     if (vel) { p.v.x = vel[3 * q]; p.v.y = vel[3 * q + 1]; p.v.z = vel[3 * q + 2]; }
@@ -1019,12 +1182,113 @@ static lpr_status read_forces_impl(lpr_bed* b, int32_t bed, float* force, float*
   if (st != LPR_OK) return st;
   const HostBed& H = b->hb[bed];
   std::vector<float4> f(H.npad), t(H.npad);
+  std::vector<int32_t> sid(H.npad);
   HIPTRY(hipMemcpy(f.data(), b->d.frc + H.p0, sizeof(float4) * H.npad, hipMemcpyDeviceToHost));
   HIPTRY(hipMemcpy(t.data(), b->d.trq + H.p0, sizeof(float4) * H.npad, hipMemcpyDeviceToHost));
-  for (int64_t off = 0; off < H.n; ++off) {
-    const int64_t q = H.perm[off];
+  HIPTRY(hipMemcpy(sid.data(), b->d.sid + H.p0, sizeof(int32_t) * H.npad, hipMemcpyDeviceToHost));
+  for (int64_t off = 0; off < H.npad; ++off) {
+    if (sid[off] < 0) continue;
+    const int64_t q = sid[off];
     if (force) { force[3 * q] = f[off].x; force[3 * q + 1] = f[off].y; force[3 * q + 2] = f[off].z; }
     if (torque) { torque[3 * q] = t[off].x; torque[3 * q + 1] = t[off].y; torque[3 * q + 2] = t[off].z; }
+  }
+  return LPR_OK;
+}
+
+// Per-contact loads are compacted on the device into a workspace: per
+// particle its contact count, their exclusive scan (and the scan's tile
+// sums), then the records; the records are copied to the caller's buffer and
+// put in canonical order there.
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static size_t load_head_bytes(int64_t np) {
+  return al256(4 * (size_t)np) + al256(4 * ((size_t)np + 1)) + al256(4 * scan_tmp_elems(np));
+}
+
+// Counts and scans the last step's contacts of bed `bed` into ws; *total
+// gets their number.
+static lpr_status load_count(lpr_bed* b, int32_t bed, char* ws, int64_t* total) {
+  const HostBed& H = b->hb[bed];
+  const int64_t np = H.npad;
+  uint32_t* cnt = (uint32_t*)ws;
+  uint32_t* off = (uint32_t*)(ws + al256(4 * (size_t)np));
+  uint32_t* tmp = (uint32_t*)(ws + al256(4 * (size_t)np) + al256(4 * ((size_t)np + 1)));
+  launch_load_count(b->d, b->l, b->h, H.p0, np, H.nwall, cnt, b->stream);
+  launch_scan(cnt, off, tmp, np, b->stream);
+  uint32_t tot = 0;
+  HIPTRY(hipMemcpyAsync(&tot, off + np, sizeof(uint32_t), hipMemcpyDeviceToHost, b->stream));
+  HIPTRY(hipStreamSynchronize(b->stream));
+  HIPTRY(hipGetLastError());
+  *total = (b->host_steps > 0) ? (int64_t)tot : 0;
+  return LPR_OK;
+}
+
+// Writes the counted records to rec (device, after the head of ws), copies
+// them to out and sorts them there by (a, b).
+static lpr_status load_pack(lpr_bed* b, int32_t bed, char* ws, lpr_contact_load* rec, int64_t total,
+                     lpr_contact_load* out) {
+  if (total == 0) return LPR_OK;
+  const HostBed& H = b->hb[bed];
+  const int64_t np = H.npad;
+  const uint32_t* off = (const uint32_t*)(ws + al256(4 * (size_t)np));
+  launch_load_pack(b->d, b->l, b->h, H.p0, np, H.nwall, off, rec, b->stream);
+  HIPTRY(hipMemcpyAsync(out, rec, sizeof(lpr_contact_load) * (size_t)total, hipMemcpyDeviceToHost, b->stream));
+  HIPTRY(hipStreamSynchronize(b->stream));
+  HIPTRY(hipGetLastError());
+  std::sort(out, out + total, [](const lpr_contact_load& x, const lpr_contact_load& y) {
+    return x.a < y.a || (x.a == y.a && x.b < y.b);
+  });
+  return LPR_OK;
+}
+
+static lpr_status loads_readable(lpr_bed* b) {
+  if (!b->record) return fail(LPR_E_STATE, "bed was created without record_forces");
+  if (b->stepper != LPR_STEPPER_EXPLICIT) return fail(LPR_E_STATE, "per-contact loads are kept by the explicit step");
+  return LPR_OK;
+}
+
+static lpr_status read_contact_loads_impl(lpr_bed* b, int32_t bed, lpr_contact_load* out, int64_t capacity,
+                                          int64_t* n_total) {
+  if (!b) return fail(LPR_E_INVAL, "null bed");
+  lpr_status st = loads_readable(b);
+  if (st != LPR_OK) return st;
+  if ((st = sync_check(b)) != LPR_OK) return st;
+  const int64_t np = b->hb[bed].npad;
+  const size_t head = load_head_bytes(np);
+  auto ensure = [&](size_t need) -> bool {
+    if (b->ld_ws_bytes >= need) return true;
+    b->dfree(b->ld_ws);
+    b->ld_ws = (char*)b->dalloc(need);
+    b->ld_ws_bytes = b->ld_ws ? need : 0;
+    return b->ld_ws != nullptr;
+  };
+  if (!ensure(head)) return fail(LPR_E_NOMEM, "per-contact read workspace");
+  int64_t total = 0;
+  if ((st = load_count(b, bed, b->ld_ws, &total)) != LPR_OK) return st;
+  if (n_total) *n_total = total;
+  if (total > capacity) return fail(LPR_E_CAPACITY, "contact buffer too small");
+  if (total == 0) return LPR_OK;
+  const size_t need = head + sizeof(lpr_contact_load) * (size_t)total;
+  if (b->ld_ws_bytes < need) {
+    // the counts and their scan live at the head of the workspace: recount
+    // in the larger one
+    if (!ensure(need)) return fail(LPR_E_NOMEM, "per-contact read workspace");
+    if ((st = load_count(b, bed, b->ld_ws, &total)) != LPR_OK) return st;
+  }
+  return load_pack(b, bed, b->ld_ws, (lpr_contact_load*)(b->ld_ws + head), total, out);
+}
+
+static lpr_status read_wall_pose_impl(lpr_bed* b, int32_t bed, int32_t wall, double out15[15]) {
+  if (!b || !out15) return fail(LPR_E_INVAL, "null argument");
+  const HostBed& H = b->hb[bed];
+  if (wall < 0 || wall >= H.nwall) return fail(LPR_E_INVAL, "wall out of range");
+  HIPTRY(hipStreamSynchronize(b->stream));
+  WallPose P;
+  HIPTRY(hipMemcpy(&P, b->d.walls + H.wall0 + wall, sizeof(WallPose), hipMemcpyDeviceToHost));
+  for (int a = 0; a < 3; ++a) {
+    out15[a] = P.o[a];
+    out15[3 + a] = P.nu[a];
+    for (int c = 0; c < 3; ++c) out15[6 + 3 * c + a] = P.e[c][a];
   }
   return LPR_OK;
 }
@@ -1148,6 +1412,7 @@ lpr_status lpr_get_stats(lpr_bed* b, lpr_stats* out) {
   out->max_owner_slots = (int32_t)stat[0];
   out->skin_trips = b->skin_trips;
   out->adjoint_interval = b->adj_interval;
+  out->sorts = b->sorts;
   return LPR_OK;
 }
 
@@ -1161,8 +1426,10 @@ lpr_status lpr_batch_create(const lpr_bed_desc* const* descs, int32_t n_beds, co
   for (int q = 1; q < n_beds; ++q)
     if (!descs || !descs[q] || !descs[0] || descs[q]->rebuild_every != descs[0]->rebuild_every ||
         descs[q]->skin != descs[0]->skin || descs[q]->block != descs[0]->block ||
-        descs[q]->record_forces != descs[0]->record_forces || descs[q]->persistent != descs[0]->persistent)
-      return fail(LPR_E_INVAL, "beds of a batch share rebuild_every, skin, block, persistent, record_forces");
+        descs[q]->record_forces != descs[0]->record_forces || descs[q]->persistent != descs[0]->persistent ||
+        descs[q]->sort_every != descs[0]->sort_every || descs[q]->input_order != descs[0]->input_order)
+      return fail(LPR_E_INVAL, "beds of a batch share rebuild_every, skin, block, persistent, record_forces, "
+                               "sort_every, input_order");
   return create_impl(descs, n_beds, alloc, hip_stream, out);
 }
 
@@ -1484,7 +1751,9 @@ lpr_status lpr_adjoint_window(lpr_bed* b, int64_t n_steps, int32_t ckpt_every, i
   b->gexec = nullptr;
   b->graph = nullptr;
   b->has_graph = false;
+  b->sort_hold = true;  // one storage order for the window: the records index particles by it
   auto restore_mode = [&]() {
+    b->sort_hold = false;
     b->R = R0;
     b->R_eff = Reff0;
     b->skin = skin0;
@@ -1628,6 +1897,19 @@ lpr_status lpr_read_forces(lpr_bed* b, float* force, float* torque) { return rea
 lpr_status lpr_batch_read_forces(lpr_bed* b, int32_t bed, float* force, float* torque) {
   if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
   return read_forces_impl(b, bed, force, torque);
+}
+lpr_status lpr_read_contact_loads(lpr_bed* b, lpr_contact_load* out, int64_t capacity, int64_t* n_total) {
+  return read_contact_loads_impl(b, 0, out, capacity, n_total);
+}
+lpr_status lpr_batch_read_contact_loads(lpr_bed* b, int32_t bed, lpr_contact_load* out, int64_t capacity,
+                                        int64_t* n_total) {
+  if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
+  return read_contact_loads_impl(b, bed, out, capacity, n_total);
+}
+lpr_status lpr_read_wall_pose(lpr_bed* b, int32_t wall, double out15[15]) { return read_wall_pose_impl(b, 0, wall, out15); }
+lpr_status lpr_batch_read_wall_pose(lpr_bed* b, int32_t bed, int32_t wall, double out15[15]) {
+  if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
+  return read_wall_pose_impl(b, bed, wall, out15);
 }
 lpr_status lpr_read_reaction(lpr_bed* b, int32_t body, double out6[6]) { return read_reaction_impl(b, 0, body, out6); }
 lpr_status lpr_batch_read_reaction(lpr_bed* b, int32_t bed, int32_t body, double out6[6]) {

@@ -82,6 +82,23 @@ def emit(rng, layer: Layer, side: float, z_start: float, count: int):
     return pos, rad
 
 
+def relax_spec(pos, rad, vel, omg, side, params) -> "beds.BedSpec":
+    """The bed a relaxation steps: the spheres in a box periodic in x and y
+    (side `side`, or (Lx, Ly)) on a frictionless floor, with `params`."""
+    n = len(rad)
+    Lx, Ly = (side, side) if np.isscalar(side) else side
+    return beds.BedSpec(pos=np.ascontiguousarray(pos, np.float64), radius=np.asarray(rad, np.float32),
+                        vel=np.asarray(vel, np.float32).reshape(n, 3), omega=np.asarray(omg, np.float32).reshape(n, 3),
+                        box=(Lx, Ly, 0.0), periodic=3, params=params, walls=[beds.floor_wall(0.0, 0.0)],
+                        bodies=[beds.Body()], info={"workload": "emission"})
+
+
+def relax_lists(spec) -> dict:
+    """Broad-phase settings of a relaxation: candidate lists with a skin of a
+    quarter of the smallest radius, rebuilt every 5 steps."""
+    return {"rebuild_every": 5, "skin": 0.25 * float(np.min(spec.radius))}
+
+
 def relax(pos, rad, vel, omg, side, params, v_tol=0.02, chunk=4000, max_steps=200_000, min_steps=0):
     """Steps the spheres on the GPU (periodic sides of length `side`, or
     (Lx, Ly), frictionless floor, the paper's relaxation friction) in chunks
@@ -90,14 +107,8 @@ def relax(pos, rad, vel, omg, side, params, v_tol=0.02, chunk=4000, max_steps=20
     compact), at most max_steps (rounded up to whole chunks).  Returns
     positions, velocities, spins and the steps taken."""
     from .lprdem import Bed
-    n = len(rad)
-    Lx, Ly = (side, side) if np.isscalar(side) else side
-    spec = beds.BedSpec(pos=np.ascontiguousarray(pos, np.float64), radius=np.asarray(rad, np.float32),
-                        vel=np.asarray(vel, np.float32).reshape(n, 3), omega=np.asarray(omg, np.float32).reshape(n, 3),
-                        box=(Lx, Ly, 0.0), periodic=3, params=params, walls=[beds.floor_wall(0.0, 0.0)],
-                        bodies=[beds.Body()], info={"workload": "emission"})
-    rmin = float(np.min(rad))
-    bed = Bed(spec, rebuild_every=5, skin=0.25 * rmin)
+    spec = relax_spec(pos, rad, vel, omg, side, params)
+    bed = Bed(spec, **relax_lists(spec))
     steps = 0
     try:
         while True:

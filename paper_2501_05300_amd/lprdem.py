@@ -25,8 +25,10 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device erro
 
 # Entry points declared in include/lprdem.h
 _PER_BED = ("get_state", "set_state", "get_history", "set_history", "read_contacts", "read_forces", "read_reaction",
-            "reaction_window", "read_body", "set_clock", "get_clock", "set_body_state")
-SYMBOLS = ("lpr_bed_create", "lpr_bed_destroy", "lpr_step", "lpr_step_profiled", "lpr_sync", "lpr_get_stats",
+            "reaction_window", "read_body", "set_clock", "get_clock", "set_body_state", "read_contact_loads",
+            "read_wall_pose")
+SYMBOLS = ("lpr_bed_create", "lpr_bed_destroy", "lpr_step", "lpr_step_profiled", "lpr_step_phases", "lpr_sync",
+           "lpr_get_stats",
            "lpr_status_str", "lpr_last_error", "lpr_batch_create", "lpr_batch_size", "lpr_set_launch",
            "lpr_autotune", "lpr_set_contact_params", "lpr_adjoint_window", "lpr_set_stepper") + tuple("lpr_" + f for f in _PER_BED) + tuple("lpr_batch_" + f for f in _PER_BED)
 
@@ -70,7 +72,7 @@ class _Desc(ctypes.Structure):
                 ("n_bodies", ctypes.c_int32), ("bodies", ctypes.c_void_p), ("params", _Params),
                 ("rebuild_every", ctypes.c_int32), ("skin", ctypes.c_float), ("band_ratio", ctypes.c_float),
                 ("cell_factor", ctypes.c_float), ("block", ctypes.c_int32), ("record_forces", ctypes.c_int32),
-                ("persistent", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("sort_every", ctypes.c_int32), ("input_order", ctypes.c_int32)]
 
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
@@ -90,6 +92,10 @@ class _History(ctypes.Structure):
                 ("xi_r", ctypes.c_float * 3)]
 
 
+# numpy view of lpr_contact_load: 48 bytes, no padding
+_LOAD_DT = np.dtype([("a", "<i8"), ("b", "<i8"), ("f", "<f4", (3,)), ("m", "<f4", (3,)), ("fn", "<f4"),
+                     ("reserved", "<f4")])
+
 # numpy view of lpr_history (the struct above): 40 bytes, no padding
 _HISTORY_DT = np.dtype([("o", "<i8"), ("p", "<i8"), ("v", "<f4", (6,))])
 assert _HISTORY_DT.itemsize == ctypes.sizeof(_History)
@@ -104,7 +110,7 @@ class _Stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("contacts", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("rebuilds", ctypes.c_int64), ("levels", ctypes.c_int32), ("cells", ctypes.c_int64),
                 ("max_owner_slots", ctypes.c_int32), ("skin_trips", ctypes.c_int64),
-                ("adjoint_interval", ctypes.c_int32)]
+                ("adjoint_interval", ctypes.c_int32), ("sorts", ctypes.c_int64)]
 
 
 _lib = None
@@ -124,13 +130,14 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "lpr_bed_create": [ctypes.POINTER(_Desc), ctypes.POINTER(_Allocator), vp, ctypes.POINTER(vp)],
         "lpr_bed_destroy": [vp], "lpr_step": [vp, i64], "lpr_sync": [vp],
-        "lpr_step_profiled": [vp, i64, vp],
+        "lpr_step_profiled": [vp, i64, vp], "lpr_step_phases": [vp, i64, vp],
         "lpr_get_state": [vp, vp, vp, vp], "lpr_set_state": [vp, vp, vp, vp],
         "lpr_get_history": [vp, vp, i64, ctypes.POINTER(i64)], "lpr_set_history": [vp, vp, i64],
         "lpr_read_contacts": [vp, vp, i64, ctypes.POINTER(i64)], "lpr_read_forces": [vp, vp, vp],
         "lpr_read_reaction": [vp, i32, vp], "lpr_reaction_window": [vp, i32, vp, ctypes.POINTER(i64), i32],
         "lpr_read_body": [vp, i32, vp, vp], "lpr_set_clock": [vp, i64], "lpr_get_clock": [vp, ctypes.POINTER(i64)],
         "lpr_set_body_state": [vp, i32, d, d], "lpr_get_stats": [vp, ctypes.POINTER(_Stats)],
+        "lpr_read_contact_loads": [vp, vp, i64, ctypes.POINTER(i64)], "lpr_read_wall_pose": [vp, i32, vp],
     }
     for f in _PER_BED:
         args = sig["lpr_" + f]
@@ -183,7 +190,8 @@ def _ptr(a):
 class _DescHolder:
     """A filled lpr_bed_desc plus the arrays it points to (kept alive)."""
 
-    def __init__(self, spec, rebuild_every, skin, band_ratio, cell_factor, block, record_forces, persistent=False):
+    def __init__(self, spec, rebuild_every, skin, band_ratio, cell_factor, block, record_forces, persistent=False,
+                 sort_every=0, input_order=False):
         self.pos = np.ascontiguousarray(spec.pos, np.float64)
         self.rad = np.ascontiguousarray(spec.radius, np.float32)
         self.vel = np.ascontiguousarray(spec.vel, np.float32)
@@ -221,6 +229,8 @@ class _DescHolder:
         D.block = int(block)
         D.record_forces = 1 if record_forces else 0
         D.persistent = 1 if persistent else 0
+        D.sort_every = int(sort_every)
+        D.input_order = 1 if input_order else 0
         self.desc = D
 
 
@@ -291,6 +301,17 @@ class _Stepper:
         out = np.zeros(4)
         _check(_lib.lpr_step_profiled(self._h, int(n), _ptr(out)), "lpr_step_profiled")
         return {"rebuild": out[0], "step": out[1], "advance": out[2], "total": out[3]}
+
+    PHASES = ("binning", "resort", "cell_lists", "search", "reverse_lists", "contact_step", "body_reduction")
+
+    def step_phases(self, n):
+        """Steps n times with HIP events at every phase boundary; returns
+        summed milliseconds per phase (PHASES) and "total"."""
+        out = np.zeros(8)
+        _check(_lib.lpr_step_phases(self._h, int(n), _ptr(out)), "lpr_step_phases")
+        res = {k: float(out[q]) for q, k in enumerate(self.PHASES)}
+        res["total"] = float(out[7])
+        return res
 
     def sync(self):
         _check(_lib.lpr_sync(self._h), "lpr_sync")
@@ -376,6 +397,25 @@ class _Stepper:
         self._call("read_forces", bed, _ptr(F), _ptr(T))
         return F, T
 
+    def contact_loads(self, bed=0):
+        """Per contact of the last step, in contacts() order: (pairs (k, 2),
+        force on particle a (k, 3), rolling moment on a (k, 3), F_n (k,))."""
+        tot = ctypes.c_int64(0)
+        try:
+            self._call("read_contact_loads", bed, None, 0, ctypes.byref(tot))
+        except CapacityError:
+            pass
+        arr = np.zeros(max(1, tot.value), _LOAD_DT)
+        self._call("read_contact_loads", bed, arr.ctypes.data, tot.value, ctypes.byref(tot))
+        arr = arr[:tot.value]
+        return np.stack([arr["a"], arr["b"]], 1), arr["f"].copy(), arr["m"].copy(), arr["fn"].copy()
+
+    def wall_pose(self, wall, bed=0):
+        """World pose of a wall at the current clock: origin, normal, frame rows (3, 3)."""
+        out = np.zeros(15)
+        self._call("read_wall_pose", bed, int(wall), _ptr(out))
+        return out[0:3], out[3:6], out[6:15].reshape(3, 3)
+
     def reaction(self, body, bed=0):
         out = np.zeros(6)
         self._call("read_reaction", bed, int(body), _ptr(out))
@@ -409,13 +449,16 @@ class Bed(_Stepper):
     """A graded bed stepped by the HIP library on one GPU.
 
     spec: paper_2501_05300_amd.beds.BedSpec.  rebuild_every / skin /
-    band_ratio / cell_factor / block / persistent choose how contacts are
-    found and how the step kernel is launched (never which contacts or what
-    results); record_forces keeps per-particle contact forces for forces().
+    band_ratio / cell_factor / block / persistent / sort_every / input_order
+    choose how contacts are found, how particles are ordered in memory and
+    how the step kernel is launched (never which contacts or what results);
+    record_forces keeps per-particle contact forces for forces() and
+    per-contact loads for contact_loads().
     """
 
     def __init__(self, spec, rebuild_every=1, skin=0.0, band_ratio=0.0, cell_factor=0.0, block=0,
-                 record_forces=False, persistent=False, device=0, torch_memory=True):
+                 record_forces=False, persistent=False, device=0, torch_memory=True, sort_every=0,
+                 input_order=False):
         import torch
         self.device = _gpu_or_raise(device)
         L = load_library()
@@ -423,7 +466,7 @@ class Bed(_Stepper):
         self.n = spec.n
         self.stream = torch.cuda.Stream(self.device)
         self._holder = _DescHolder(spec, rebuild_every, skin, band_ratio, cell_factor, block, record_forces,
-                                   persistent)
+                                   persistent, sort_every, input_order)
         self._mem = _TorchMemory(self.device, self.stream)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -443,7 +486,7 @@ class Batch(_Stepper):
     _batch = True
 
     def __init__(self, specs, rebuild_every=1, skin=0.0, band_ratio=0.0, cell_factor=0.0, block=0,
-                 record_forces=False, persistent=False, device=0, layouts=None):
+                 record_forces=False, persistent=False, device=0, layouts=None, sort_every=0, input_order=False):
         import torch
         self.device = _gpu_or_raise(device)
         L = load_library()
@@ -452,7 +495,8 @@ class Batch(_Stepper):
         self._holders = []
         for q, s in enumerate(self.specs):
             br, cf = (layouts[q] if layouts is not None else (band_ratio, cell_factor))
-            self._holders.append(_DescHolder(s, rebuild_every, skin, br, cf, block, record_forces, persistent))
+            self._holders.append(_DescHolder(s, rebuild_every, skin, br, cf, block, record_forces, persistent,
+                                             sort_every, input_order))
         arr = (ctypes.POINTER(_Desc) * len(self._holders))(*[ctypes.pointer(h.desc) for h in self._holders])
         self._mem = _TorchMemory(self.device, self.stream)
         h = ctypes.c_void_p()

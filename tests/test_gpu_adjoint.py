@@ -128,3 +128,92 @@ def test_autograd_function():
     (gt,) = torch.autograd.grad(J, theta)
     assert torch.isfinite(gt).all() and float(gt.abs().sum()) > 0
     assert float(J) > 0
+
+
+def loaded_graded_bed(n, side, seed, pre, full_width, load=0.0, max_steps=400_000):
+    """A graded bed (r0 1.5 mm, L 20 mm, k 1, cap 8 r0, 0.2 m deep) relaxed on
+    the GPU, under a plate pushed at 0.01 m/s for at least `pre` steps and
+    until its mean reaction over the last 10,000 steps exceeds `load` N (at
+    most max_steps), so that it carries load; returns the spec and the GPU
+    bed (skin lists)."""
+    from paper_2501_05300_amd.lprdem import Bed
+    from parity_util import relax_on_gpu
+    spec = beds.graded_bed(n, r0=1.5e-3, L=0.02, k=1.0, cap=8.0, depth=0.2, side=side, seed=seed)
+    spec = relax_on_gpu(spec, 40_000)
+    spec = beds.add_plate(spec, diameter=0.1, speed=0.01, full_width=full_width)
+    body = spec.info["plate_body"]
+    bed = Bed(spec, rebuild_every=10, skin=0.25 * float(spec.radius.min()))
+    done = 0
+    while True:
+        bed.reaction_window(body, reset=True)
+        bed.step(10_000)
+        bed.sync()
+        done += 10_000
+        sm, k = bed.reaction_window(body)
+        if (done >= pre and sm[2] / k > load) or done >= max_steps:
+            break
+    print("plate pushed", done, "steps; mean reaction", sm[2] / k)
+    return spec, bed
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_on_the_2k_graded_copy_matches_the_oracle():
+    """The adjoint workload's 2,000-sphere copy (0.0671 m periodic side, a
+    full-width plate pushed at 0.01 m/s): the 2,000-step window with a
+    checkpoint every 100 steps (20 segments, spring adjoints remapped across
+    every rebuild) against the oracle's FP64 forward-mode gradient from the
+    same state."""
+    spec, bed = loaded_graded_bed(2000, 0.0671, 7, 20_000, True, load=0.05)
+    ob = oracle_from_gpu(spec, bed)
+    J, g = bed.adjoint_window(2000, 100, 1)
+    assert bed.stats()["adjoint_interval"] == 100
+    Jo, go = ob.tangent_window(2000, 1, 2)
+    print("gpu", J, g, "oracle", Jo, go)
+    assert abs(Jo) > 1e-3
+    assert abs(J - Jo) <= 1e-3 * abs(Jo)
+    scale = np.abs(go) + 1e-3 * abs(Jo) / np.array([1.0, 0.3, 0.02])
+    assert np.all(np.abs(g - go) <= 1e-3 * scale), (g, go)
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_on_the_50k_graded_bed_matches_central_differences():
+    """The adjoint workload itself: a 50,000-sphere graded bed (0.336 m
+    side) under a 0.1 m plate pushed at 0.01 m/s, 2,000-step window with a
+    checkpoint every 100 steps, against GPU central differences of the same
+    window (relative steps 1e-4 and 1e-3 of each parameter; the one closer to
+    the adjoint is taken, as FP32 trajectories put rounding noise on the
+    smaller one) within 1e-2."""
+    from paper_2501_05300_amd.lprdem import Bed
+    spec, bed = loaded_graded_bed(50_000, 0.336, 50, 50_000, False)
+    body = spec.info["plate_body"]
+    x, v, w = bed.state()
+    keys, vals = bed.history()
+    clock = bed.clock()
+    T = 2000
+    J, g = bed.adjoint_window(T, 100, body)
+    print("adjoint", J, g, "interval", bed.stats()["adjoint_interval"])
+    skin = 0.25 * float(spec.radius.min())
+
+    def window_mean(name, value):
+        s2 = spec.copy()
+        s2.params = spec.params.replace(**{name: value})
+        b = Bed(s2, rebuild_every=10, skin=skin)
+        b.set_state(x, v, w)
+        b.set_history(keys, vals)
+        b.set_clock(clock)
+        b.reaction_window(body, reset=True)
+        b.step(T)
+        sm, k = b.reaction_window(body)
+        b.close()
+        return sm[2] / k
+
+    assert J > 0
+    for q, name in enumerate(("s_k", "mu_t", "mu_r")):
+        p0 = getattr(spec.params, name)
+        fds = []
+        for rel in (1e-4, 1e-3):
+            h = rel * p0
+            fds.append((window_mean(name, p0 + h) - window_mean(name, p0 - h)) / (2 * h))
+        fd = min(fds, key=lambda f: abs(f - g[q]))
+        print(name, g[q], fds)
+        assert abs(g[q] - fd) <= 1e-2 * max(abs(fd), 1e-3 * abs(J) / p0), (name, g[q], fds)

@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 from paper_2501_05300_amd import beds
-from parity_util import compare_one_step, oracle_pairs
+from parity_util import assert_parity, compare_one_step, oracle_pairs
 
 pytestmark = pytest.mark.gpu
 
@@ -58,8 +58,7 @@ def test_batch_bed_parity_with_oracle():
     for q in (1, 2):
         res = compare_one_step(specs[q], View(batch, q))
         print(q, res)
-        assert res["contacts_equal"], res
-        assert res["force_rel"] < 1e-5 and res["torque_rel"] < 1e-5
+        assert_parity(res, 1e-5)
 
 
 @pytest.mark.parametrize("block,persistent", [(64, False), (128, True), (256, True), (64, True)])

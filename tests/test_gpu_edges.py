@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_2501_05300_amd import beds
-from parity_util import compare_one_step
+from parity_util import assert_parity, compare_one_step
 
 pytestmark = pytest.mark.gpu
 
@@ -105,10 +105,9 @@ def test_exactly_as_many_partners_as_slots():
     res = compare_one_step(spec, bed)
     bed.sync()  # raises if a fault latched
     print({k: v for k, v in res.items() if k not in ("only_gpu", "only_oracle")})
-    assert res["contacts_equal"], res
+    assert_parity(res, 1e-5)
     got = bed.contacts()
     assert int(np.sum(got[:, 0] == 0)) == 16  # stable id 0 is the small sphere
-    assert res["force_rel"] < 1e-5
     # from rest there is no tangential motion, so the torques vanish up to
     # rounding: compare them with the force scale times the lever arm
     F, T = bed.forces()
@@ -133,11 +132,10 @@ def test_crowded_cells_take_the_exact_walk():
     res = compare_one_step(spec, bed)
     bed.sync()
     print({k: v for k, v in res.items() if k not in ("only_gpu", "only_oracle")})
-    assert res["contacts_equal"], res
+    assert_parity(res, 1e-5)
     got = bed.contacts()
     large = np.arange(n_small, n_small + n_large)
     assert int(np.isin(got[:, 1], large).sum()) > 100 * n_large  # long partner-side lists
-    assert res["force_rel"] < 1e-5
     # from rest the torques vanish up to rounding (see above)
     F, T = bed.forces()
     assert float(np.abs(T).max()) <= 1e-5 * float(np.abs(F).max()) * 2.2e-3
@@ -153,8 +151,8 @@ def test_coincident_spheres_match_oracle():
     bed = Bed(spec, record_forces=True)
     res = compare_one_step(spec, bed)
     print(res)
-    assert res["contacts_equal"] and res["n_contacts"] == 3
-    assert res["force_rel"] < 1e-5 and res["torque_rel"] < 1e-5
+    assert_parity(res, 1e-5)
+    assert res["n_contacts"] == 3
     F, _ = bed.forces()
     # stable id 0 owns the coincident pair (equal radii, smaller id) and is
     # pushed along -n = -z, its partner along +z

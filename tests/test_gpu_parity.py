@@ -11,7 +11,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2501_05300_amd import beds
-from parity_util import compare_one_step, masses, oracle_pairs, rel_norm
+from parity_util import assert_parity, compare_one_step, masses, oracle_pairs, rel_norm
 
 pytestmark = pytest.mark.gpu
 
@@ -44,10 +44,8 @@ def test_first_step_matches_oracle(seed, periodic):
     bed = gpu_bed(spec)
     res = compare_one_step(spec, bed)
     print(res)
-    assert res["contacts_equal"], res
+    assert_parity(res, FTOL)
     assert res["n_contacts"] > 500
-    assert res["force_rel"] < FTOL and res["torque_rel"] < FTOL
-    assert res["reaction0_rel"] < FTOL and res["reaction1_rel"] < FTOL
 
 
 def test_two_layer_bed_history_parity():
@@ -63,9 +61,7 @@ def test_two_layer_bed_history_parity():
     for _ in range(3):
         res = compare_one_step(spec, bed)
         print(res)
-        assert res["contacts_equal"], res
-        assert res["force_rel"] < FTOL and res["torque_rel"] < FTOL
-        assert res["reaction0_rel"] < FTOL
+        assert_parity(res, FTOL)
         bed.step(50)
 
 
@@ -150,11 +146,9 @@ def test_plate_reaction_parity():
     bed.step(400)
     res = compare_one_step(spec, bed)
     print(res)
-    assert res["contacts_equal"], res
-    assert res["force_rel"] < FTOL
+    assert_parity(res, FTOL)
     R = bed.reaction(1)
     assert abs(R[2]) > 0
-    assert res["reaction1_rel"] < FTOL
 
 
 @pytest.mark.parametrize("skin,every", [(2e-4, 10), (1e-9, 7)])
@@ -172,7 +166,9 @@ def test_skin_lists_step_bitwise_like_every_step_search(skin, every):
     xb, vb, wb = b.state()
     assert np.array_equal(xa, xb) and np.array_equal(va, vb) and np.array_equal(wa, wb)
     assert np.array_equal(a.contacts(), b.contacts())
-    np.testing.assert_array_equal(a.reaction(1), b.reaction(1))
+    # the two beds re-sort their storage at different steps, so the FP64
+    # block sums of the plate reaction add the same terms in another order
+    np.testing.assert_allclose(a.reaction(1), b.reaction(1), rtol=1e-12, atol=1e-12 * abs(a.reaction(1)[2]))
     st = b.stats()
     print(st)
     if skin < 1e-6:
@@ -197,9 +193,8 @@ def test_grousered_ring_parity():
     for _ in range(2):
         res = compare_one_step(spec, bed)
         print(res)
-        assert res["contacts_equal"], res
-        assert res["force_rel"] < FTOL and res["torque_rel"] < FTOL
-        assert res["reaction1_rel"] < FTOL
+        assert_parity(res, FTOL)
+        assert abs(bed.reaction(1)[5]) > 0  # the drive torque is compared too
         bed.step(100)
     n_ring = int(np.sum(bed.contacts()[:, 1] <= -2))
     assert n_ring > 0
@@ -228,7 +223,5 @@ def test_full_size_graded_bed_step_parity():
     bed.step(3)
     res = compare_one_step(spec, bed)
     print({k: v for k, v in res.items() if k not in ("only_gpu", "only_oracle")})
-    assert res["contacts_equal"], res
+    assert_parity(res, FTOL)
     assert res["n_contacts"] > spec.n  # a bed in contact, not a falling cloud
-    assert res["force_rel"] < FTOL and res["torque_rel"] < FTOL
-    assert res["reaction0_rel"] < FTOL

@@ -470,3 +470,40 @@ def test_stuck_spring_co_rotates_with_a_rigid_pair(dtheta, axial):
         else:
             np.testing.assert_allclose(xi, rot_z(th) @ xi0, rtol=0, atol=(k + 1) * dtheta ** 2 * L0)
         np.testing.assert_allclose(vals[0, 3:], 0.0, atol=1e-25)
+
+
+def test_contact_term_scales_bound_the_loads():
+    """The per-contact scales the GPU parity bounds are taken against: the
+    summed magnitudes of the law's force terms are at least the contact
+    force (|F_t - F_n n| <= |F_t| + F_n, each no larger than its terms; a cap
+    only shrinks), the moment terms at least the rolling moment; and a
+    contact at rest with no history has exactly its elastic term, k_n
+    delta^{3/2}."""
+    import math
+    spec = beds.random_cloud(600, 0.03, 0.02, 0.6e-3, 2.0e-3, seed=9, periodic=3, vel_scale=0.05,
+                             omega_scale=20.0, params=beds.Params(E=1e7))
+    b = O.OracleBed(spec)
+    b.step(3)
+    F, M, fn = b.last_contact_loads()
+    sF, sM = b.last_contact_scales()
+    assert len(fn) > 100
+    assert np.all(sF >= np.linalg.norm(F, axis=1) * (1 - 1e-12))
+    assert np.all(sM >= np.linalg.norm(M, axis=1) * (1 - 1e-12))
+    assert np.any(sF > 1.01 * np.linalg.norm(F, axis=1))   # terms that partly cancel are counted whole
+    # two spheres at rest, overlapping by delta: F = F_n = k_n delta^{3/2}
+    r, delta = 1e-3, 1e-6
+    p = beds.paper_params()
+    two = beds.BedSpec(pos=np.array([[0.01, 0.01, 0.01], [0.01 + 2 * r - delta, 0.01, 0.01]]),
+                       radius=np.full(2, r, np.float32), vel=np.zeros((2, 3), np.float32),
+                       omega=np.zeros((2, 3), np.float32), box=(0.05, 0.05, 0.0), periodic=3, params=p,
+                       walls=[], bodies=[beds.Body()])
+    ob = O.OracleBed(two)
+    ob.step(1)
+    F2, _, fn2 = ob.last_contact_loads()
+    sF2, sM2 = ob.last_contact_scales()
+    rr = float(np.float32(r))
+    d = (2 * rr) - (0.01 + 2 * r - delta - 0.01)
+    Estar = p.E / (2 * (1 - p.nu ** 2))
+    kn = Estar * math.sqrt(rr) / 3.0
+    assert sF2[0] == pytest.approx(kn * d ** 1.5, rel=1e-9)
+    assert sF2[0] == pytest.approx(fn2[0], rel=1e-12) and sM2[0] == 0.0
