@@ -40,27 +40,65 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def counter_traffic(n_particles):
-    """HBM bytes per launch of the step kernel and per whole step (every-step
-    search, skin lists) from the committed rocprofv3 counter record, when it
-    was taken on the current kernel code; otherwise Nones."""
+def counter_record(n_particles):
+    """The committed rocprofv3 counter record of the metric bed (HBM bytes per
+    launch of every kernel, every-step search and skin lists), when it was
+    taken on the current kernel code and the same bed size; else None."""
     from paper_2501_05300_amd.profile_summary import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "step_kernel_counters_metric_bed.json")
     if not os.path.exists(path):
-        return None, None, None, None
+        return None
     with open(path) as f:
         c = json.load(f)
     if c.get("kernel_source_hash") != kernel_source_hash() or c.get("n") != n_particles:
-        return None, None, None, None
-    return (c.get("hbm_bytes_per_launch"), c.get("hbm_bytes_per_launch_skin_lists"), c.get("hbm_bytes_per_step"),
-            c.get("hbm_bytes_per_step_skin_lists"))
+        return None
+    return c
 
 
-def settle_beds(specs, steps, chunk=5000):
+def kernel_traffic(rec, mode, kernel):
+    """FETCH_SIZE + WRITE_SIZE bytes per launch of one kernel from the record."""
+    if rec is None or kernel not in rec.get(mode, {}):
+        return None
+    k = rec[mode][kernel]
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
+# the kernel that does most of each timed phase (the phase's own name when it
+# is one kernel)
+PHASE_KERNEL = {"binning": "k_bin", "resort": "k_rs_scatter", "cell_lists": "k_scatter", "search": "k_search",
+                "reverse_lists": "k_rev_scatter", "contact_step": "k_step<{block}>", "body_reduction": "k_advance"}
+
+
+def host_cpu():
+    """Host CPU as the GPU machine reports it: nproc, os.cpu_count(), lscpu model."""
+    import subprocess
+    out = {"nproc": None, "cpu_count": os.cpu_count(), "model": None}
+    try:
+        out["nproc"] = int(subprocess.run(["nproc"], capture_output=True, text=True, timeout=10).stdout.strip())
+    except Exception:  # noqa: BLE001
+        pass
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name:"):
+                out["model"] = line.split(":", 1)[1].strip()
+            if line.startswith("CPU(s):"):
+                out["lscpu_cpus"] = int(line.split(":", 1)[1].strip())
+    except Exception:  # noqa: BLE001
+        pass
+    return out
+
+
+def settle_beds(specs, steps, chunk=5000, max_steps=None, rel_change=0.01):
     """Relaxes deposited beds in place (positions only), all in one batch,
     with the paper's relaxation friction (mu_t 0.1, mu_r 0.01, frictionless
     walls), extra normal damping (gamma_n = 10 dt) and dt = 5e-6 s;
     velocities are then zeroed.  Untimed preparation of the input.
+
+    Runs at least `steps` steps, then (when max_steps is given) goes on in
+    chunks until the contacts per particle change by less than rel_change
+    over a chunk of `chunk` steps, or max_steps is reached.  Returns
+    (steps run, contacts per particle at the end, whether the criterion was
+    met).
 
     The damping term is explicit: its rate c/m must stay below 2/dt.  For a
     1.35 mm sphere under a 24 mm one (overlap ~3e-5 m) gamma_n = 10 dt gives
@@ -80,20 +118,31 @@ def settle_beds(specs, steps, chunk=5000):
     done = 0
     t0 = time.perf_counter()
     ntot = sum(s.n for s in specs)
-    while done < steps:
-        k = min(chunk, steps - done)
+    cbar = prev = None
+    settled = False
+    limit = max(steps, max_steps or 0)
+    while done < limit:
+        k = min(chunk, limit - done)
         sb.step(k)
         sb.sync()
         done += k
         st = sb.stats()
-        log(f"settle {done}/{steps}: contacts/particle {st['contacts'] / ntot:.3f}, "
+        prev, cbar = cbar, st["contacts"] / ntot
+        log(f"settle {done}/{steps}: contacts/particle {cbar:.3f}, "
             f"skin trips {st['skin_trips']} ({time.perf_counter() - t0:.1f} s)")
+        if done >= steps:
+            if max_steps is None:
+                break
+            if prev is not None and cbar > 0 and abs(cbar - prev) < rel_change * cbar:
+                settled = True
+                break
     for q, spec in enumerate(specs):
         pos, _, _ = sb.state(bed=q)
         spec.pos = pos
         spec.vel = np.zeros_like(spec.vel)
         spec.omega = np.zeros_like(spec.omega)
     sb.close()
+    return done, cbar, settled
 
 
 def batch_leg(steps, warmup, settle, tune_steps):
@@ -311,11 +360,13 @@ def implicit_leg(spec, steps, warmup, n_iter):
             "simulated_s_per_wall_s": 1e-4 * steps / wall,
             "contact_sweeps_per_s": st["contacts"] * n_iter * steps / (prof["step"] / 1e3),
             "kernel_ms_per_step": {k: v / steps for k, v in prof.items()},
-            "roofline": {"bound": "hbm", "kernels": ["k_sp_contacts", "k_sp_vel"], "unit": "GB/s",
-                         "achieved": N * b_sweep / (sweep_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
-                         "frac": N * b_sweep / (sweep_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-                         "algorithmic_bytes_per_particle_sweep": b_sweep, "traffic": traffic,
-                         "traffic_frac": (traffic / (sweep_ms / 1e3) / 1e9 / HBM_PEAK_GBS) if traffic else None}}
+            # bytes the sweep kernels are designed to move (their own per-contact
+            # rows, owner sums and partner parts included), not a method minimum
+            "sweep_traffic": {"bound": "hbm", "kernels": ["k_sp_contacts", "k_sp_vel"], "unit": "GB/s",
+                              "design_GBs": N * b_sweep / (sweep_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                              "design_frac": N * b_sweep / (sweep_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                              "design_bytes_per_particle_sweep": b_sweep, "counter_bytes_per_sweep": traffic,
+                              "counter_frac": (traffic / (sweep_ms / 1e3) / 1e9 / HBM_PEAK_GBS) if traffic else None}}
 
 
 def emission_leg(seed=0):
@@ -415,11 +466,79 @@ def configs_leg(steps_c2, steps_c3, warmup, settle):
     return out
 
 
+def sort_leg(spec, steps, warmup, block):
+    """What the storage-order sort buys: the metric bed stored in its
+    (shuffled) input order, once kept frozen and once re-sorted on the
+    device at the default cadence (every 16th rebuild), then `steps` steps of
+    each with per-phase HIP events.  Same contacts and results; only where
+    the particles sit in memory differs."""
+    import torch
+    from paper_2501_05300_amd.lprdem import Bed
+    out = {}
+    for name, every in (("input_order_frozen", -1), ("input_order_resorted", 0)):
+        bed = Bed(spec, block=block, sort_every=every, input_order=True)
+        bed.step(max(warmup, 64))
+        bed.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bed.step(steps)
+        bed.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = bed.step_phases(steps)
+        st = bed.stats()
+        bed.close()
+        out[name] = {"ms_per_step": 1e3 * wall / steps, "sorts": st["sorts"],
+                     "kernel_ms_per_step": {k: v / steps for k, v in prof.items()}}
+        log(f"storage order {name}: {1e3 * wall / steps:.3f} ms/step; phases {out[name]['kernel_ms_per_step']}")
+    f, r = out["input_order_frozen"], out["input_order_resorted"]
+    out["speedup_resorted_over_frozen"] = f["ms_per_step"] / r["ms_per_step"]
+    out["steps"] = steps
+    return out
+
+
+def cpu_configs_leg(settled_2k=None):
+    """The FP64 oracle on the smaller workloads, single-threaded and on every
+    allowed host thread, on bounded samples: the two-layer bed (2,000
+    spheres, 500 steps from placement), the 200k graded bed (20 steps) and
+    the adjoint's 2,000-sphere graded copy (a 200-step window of forward-mode
+    derivatives under a full-width plate).  Particle-steps/s each."""
+    from oracle import oracle as O
+    from paper_2501_05300_amd import beds
+    env = os.environ.get("OMP_NUM_THREADS")
+    allt = int(env) if env and env.isdigit() and int(env) > 0 else (os.cpu_count() or 1)
+    out = {"host": host_cpu()}
+    c1 = beds.two_layer_bed(0)
+    c2 = beds.graded_bed(200_000, seed=0)
+    c5 = settled_2k if settled_2k is not None else beds.graded_bed(2000, side=0.0671, seed=7)
+    c5 = beds.add_plate(c5.copy(), speed=0.01, full_width=True)
+    for threads in (1, allt):
+        used = O.set_threads(threads)
+        row = {}
+        for name, spec, steps in (("two_layer_2k_500_steps", c1, 500), ("graded_200k_20_steps", c2, 20)):
+            ob = O.OracleBed(spec)
+            t0 = time.perf_counter()
+            ob.step(steps)
+            dt = time.perf_counter() - t0
+            row[name] = {"particle_steps_per_s": spec.n * steps / dt, "seconds": dt}
+        ob = O.OracleBed(c5)
+        t0 = time.perf_counter()
+        ob.tangent_window(200, c5.info["plate_body"], 2)
+        dt = time.perf_counter() - t0
+        row["adjoint_2k_window_200"] = {"particle_steps_per_s": c5.n * 200 / dt, "seconds": dt}
+        out[f"threads_{used}"] = row
+        log(f"cpu configs, {used} thread(s): {row}")
+    return out
+
+
 def cpu_baseline(spec, pos, vel, omg, keys, vals, clock, steps):
     """The FP64 oracle, as it stands, on the same bed state (bounded sample:
-    `steps` steps of the full bed)."""
+    `steps` steps of the full bed), on every host thread this job may use:
+    OMP_NUM_THREADS when the environment sets it (the GPU machine allots its CPU
+    share that way), else every CPU the process sees."""
     from oracle import oracle as O
-    threads = min(os.cpu_count() or 1, 16)
+    env = os.environ.get("OMP_NUM_THREADS")
+    threads = int(env) if env and env.isdigit() and int(env) > 0 else (os.cpu_count() or 1)
     used = O.set_threads(threads)
     ob = O.OracleBed(spec)
     ob.set_state(pos, vel, omg)
@@ -430,7 +549,8 @@ def cpu_baseline(spec, pos, vel, omg, keys, vals, clock, steps):
     dt = time.perf_counter() - t0
     return {"value": spec.n * steps / dt, "unit": "particle-steps/s", "cores": used, "kind": "oracle",
             "sample": f"{steps} FP64 oracle step(s) of the full {spec.n}-sphere bed from the GPU state after "
-                      f"warm-up, {dt:.1f} s, {used} OpenMP threads"}
+                      f"warm-up, {dt:.1f} s, {used} OpenMP threads",
+            "host": host_cpu()}
 
 
 def main():
@@ -457,6 +577,8 @@ def main():
     ap.add_argument("--implicit-sweeps", type=int, default=250)
     ap.add_argument("--calibrate-window", type=int, default=2000,
                     help="steps per experiment of the calibration leg (0: skip)")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="also time the oracle on the two-layer, 200k graded and 2k adjoint workloads (minutes)")
     ap.add_argument("--emission", action="store_true",
                     help="also build a refined bed layer by layer and report its diagnostics")
     ap.add_argument("--terramech", action="store_true",
@@ -464,7 +586,13 @@ def main():
     ap.add_argument("--configs", action="store_true",
                     help="also time the plate (200k graded) and grousered-ring (2.0M uniform vs 150k graded) beds")
     ap.add_argument("--settle", type=int, default=40000,
-                    help="relaxation steps before the measurement (paper's reduced friction, damped, dt 5e-6)")
+                    help="least relaxation steps before the measurement (paper's reduced friction, damped, dt 5e-6)")
+    ap.add_argument("--settle-max", type=int, default=200000,
+                    help="relaxation goes on until contacts per particle settle, at most this many steps")
+    ap.add_argument("--settle-tol", type=float, default=0.01,
+                    help="settled: contacts per particle change by less than this fraction over 5000 steps")
+    ap.add_argument("--sort-steps", type=int, default=200,
+                    help="timed steps of the storage-order leg (scrambled order frozen vs re-sorted; 0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this stepper runs on one GPU; --gpus must be 1 "
@@ -479,8 +607,12 @@ def main():
     t0 = time.perf_counter()
     spec = beds.metric_bed(args.n, seed=args.seed)
     log(f"bed generated: n={spec.n} side={spec.box[0]:.4f} m in {time.perf_counter() - t0:.1f} s")
+    settle = {"steps": 0, "contacts_per_particle": None, "criterion_met": False}
     if args.settle > 0:
-        settle_beds([spec], args.settle)
+        done, cbar_s, ok = settle_beds([spec], args.settle, max_steps=args.settle_max, rel_change=args.settle_tol)
+        settle = {"steps": done, "contacts_per_particle": cbar_s, "criterion_met": ok,
+                  "criterion": f"contacts per particle change < {args.settle_tol:g} relative over 5000 steps "
+                               f"(at least {args.settle}, at most {args.settle_max} steps)"}
     bed = Bed(spec, rebuild_every=args.rebuild_every, skin=args.skin, block=args.block)
     log("bed created on the GPU")
     done = 0
@@ -490,21 +622,45 @@ def main():
         bed.sync()
         done += k
         log(f"warm-up {done}/{args.warmup}")
+    # timed region: the steps as a user runs them (captured-graph cycles)
+    bed.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    prof = bed.step_profiled(args.steps)
+    bed.step(args.steps)
+    bed.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = bed.stats()
-    log(f"timed {args.steps} steps in {wall:.3f} s; kernels {prof}")
+    log(f"timed {args.steps} steps in {wall:.3f} s")
+    # the same number of steps again with HIP events at every phase boundary
+    # (direct launches) for the per-kernel durations
+    prof = bed.step_phases(args.steps)
+    log(f"phases over {args.steps} steps (ms): {prof}")
     N = spec.n
     pairs = st["contacts"]
     cbar = pairs / N
     value = N * args.steps / wall
-    step_ms = prof["step"] / args.steps
     b_alg = B_PARTICLE + B_PAIR * cbar
-    achieved = N * b_alg / (step_ms * 1e-3) / 1e9
-    traffic, traffic_skin, step_bytes, step_bytes_skin = counter_traffic(N)
+    per_step = {k: v / args.steps for k, v in prof.items()}
+    phases = {k: v for k, v in per_step.items() if k != "total"}
+    dom = max(phases, key=phases.get)
+    block = args.block or 256
+    kname = PHASE_KERNEL[dom].format(block=block)
+    rec = counter_record(N)
+    mode = "every_step" if args.rebuild_every == 1 else "skin_lists"
+
+    def roof(phase, kernel):
+        t = per_step[phase] * 1e-3
+        ach = N * b_alg / t / 1e9
+        tr = kernel_traffic(rec, mode, kernel)
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": tr, "traffic_frac": (tr / t / 1e9 / HBM_PEAK_GBS) if tr else None, "kernel": kernel,
+                "launch_ms": per_step[phase], "bytes_per_particle_step": b_alg,
+                "algorithmic_bytes_per_launch": N * b_alg}
+
+    step_bytes = None
+    if rec is not None:
+        step_bytes = rec.get("hbm_bytes_per_step" if mode == "every_step" else "hbm_bytes_per_step_skin_lists")
     out = {
         "metric": METRIC,
         "value": value,
@@ -520,17 +676,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": "graded bed, 2M spheres, r0 1.5 mm, L 20 mm, k 1, cap 8 r0, 0.2 m deep, "
                                "periodic, floor, dt 2e-6 s, settled",
-                   "settle_steps": args.settle,
-                   "n": N, "side_m": spec.box[0], "rebuild_every": args.rebuild_every, "skin_m": args.skin},
+                   "settle": settle,
+                   "n": N, "side_m": spec.box[0], "rebuild_every": args.rebuild_every, "skin_m": args.skin,
+                   "timed": "lpr_step (captured-graph cycles); per-phase durations from lpr_step_phases over "
+                            "the same number of steps right after"},
         "contacts_per_s": pairs * args.steps / wall,
         "contacts_per_particle": cbar,
-        "kernel_ms_per_step": {k: v / args.steps for k, v in prof.items()},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_GBs": traffic / (step_ms * 1e-3) / 1e9 if traffic else None,
-                     "traffic_frac": traffic / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
-                     "kernel": "k_step (fused narrow phase, law, accumulation, walls, integration)",
-                     "bytes_per_particle_step": b_alg, "algorithmic_bytes_per_launch": N * b_alg},
+        "kernel_ms_per_step": per_step,
+        # the step's algorithmic bytes over the largest phase's kernel time
+        "roofline": roof(dom, kname),
+        "roofline_step_kernel": roof("contact_step", PHASE_KERNEL["contact_step"].format(block=block)),
         "algorithmic_frac_whole_step": N * b_alg / (wall / args.steps) / 1e9 / HBM_PEAK_GBS,
         "counter_frac_whole_step": (step_bytes / (wall / args.steps) / 1e9 / HBM_PEAK_GBS) if step_bytes else None,
         "paper_context": {
@@ -548,14 +703,18 @@ def main():
         bed.sync()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof2 = bed.step_profiled(args.steps)
+        bed.step(args.steps)
+        bed.sync()
         torch.cuda.synchronize()
         wall2 = time.perf_counter() - t1
         st2 = bed.stats()
+        prof2 = bed.step_phases(args.steps)
         log(f"skin lists (every {args.secondary_every}, skin {skin:.2e} m): {args.steps} steps in {wall2:.3f} s; "
-            f"kernels {prof2}; trips {st2['skin_trips']}")
-        step2 = prof2["step"] / args.steps
+            f"phases {prof2}; trips {st2['skin_trips']}")
+        step2 = prof2["contact_step"] / args.steps
         b2 = B_PARTICLE + B_PAIR * st2["contacts"] / N
+        tr2 = kernel_traffic(rec, "skin_lists", PHASE_KERNEL["contact_step"].format(block=block))
+        sb2 = rec.get("hbm_bytes_per_step_skin_lists") if rec else None
         out["skin_lists"] = {
             "value": N * args.steps / wall2, "ms_per_step": 1e3 * wall2 / args.steps,
             "rebuild_every": args.secondary_every, "skin_m": skin, "skin_trips": st2["skin_trips"],
@@ -563,12 +722,13 @@ def main():
             "kernel_ms_per_step": {k: v / args.steps for k, v in prof2.items()},
             "step_kernel_achieved_GBs": N * b2 / (step2 * 1e-3) / 1e9,
             "step_kernel_frac": N * b2 / (step2 * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "step_kernel_traffic": traffic_skin,
-            "step_kernel_traffic_frac": traffic_skin / (step2 * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic_skin else None,
+            "step_kernel_traffic": tr2,
+            "step_kernel_traffic_frac": tr2 / (step2 * 1e-3) / 1e9 / HBM_PEAK_GBS if tr2 else None,
             "algorithmic_frac_whole_step": N * b2 / (wall2 / args.steps) / 1e9 / HBM_PEAK_GBS,
-            "counter_frac_whole_step": (step_bytes_skin / (wall2 / args.steps) / 1e9 / HBM_PEAK_GBS
-                                        if step_bytes_skin else None),
+            "counter_frac_whole_step": (sb2 / (wall2 / args.steps) / 1e9 / HBM_PEAK_GBS) if sb2 else None,
         }
+    if args.sort_steps > 0:
+        out["storage_order"] = sort_leg(spec, args.sort_steps, args.warmup, args.block)
     if args.cpu_steps > 0:
         pos, vel, omg = bed.state()
         keys, vals = bed.history()
@@ -586,6 +746,8 @@ def main():
         out["adjoint"] = adjoint_leg(50_000, args.adjoint_window, 100, args.settle, 50_000, args.seed)
     if args.calibrate_window > 0:
         out["calibration"] = calibration_leg(50_000, args.calibrate_window, 100, args.settle, args.seed)
+    if args.cpu_configs:
+        out["cpu_configs"] = cpu_configs_leg()
     if args.emission:
         out["emission"] = emission_leg(args.seed)
     if args.terramech:
