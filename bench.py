@@ -176,7 +176,7 @@ def batch_leg(steps, warmup, settle, tune_steps):
     best, trials = autotune(specs, trial_steps=tune_steps)
     log(f"autotuner: {best}")
     tb = Batch(specs, band_ratio=best["band_ratio"], cell_factor=best["cell_factor"], block=best["block"],
-               persistent=best["persistent"])
+               persistent=best["persistent"], level_cell_factor=best["level_cell_factor"])
     wall_t = timed(tb)
     tb.close()
     log(f"batched, tuned: {steps} steps in {wall_t:.3f} s")

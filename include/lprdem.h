@@ -31,7 +31,7 @@
  *   - Work is enqueued on the HIP stream given at creation.  lpr_step returns
  *     after enqueueing; every read and lpr_sync wait for the stream.
  *   - Device faults found by kernels (history-slot overflow, non-finite
- *     values) latch.  The state then stays at the last complete step; reads
+ *     values, a particle through a plane wall) latch.  The state then stays at the last complete step; reads
  *     and lpr_sync report the latched status; only lpr_get_state and
  *     lpr_bed_destroy remain usable.
  */
@@ -53,7 +53,10 @@ typedef enum {
                            history table overflowed (latched) */
   LPR_E_STATE = -5,     /* call not allowed in the current state (a latched
                            fault, or a broad-phase skin exceeded) */
-  LPR_E_NUMERIC = -6    /* non-finite force or state (latched) */
+  LPR_E_NUMERIC = -6,   /* non-finite force or state (latched) */
+  LPR_E_DOMAIN = -7     /* a particle passed through a plane wall: its
+                           centre lies beyond the plane by more than its
+                           radius (latched) */
 } lpr_status;
 
 enum { LPR_WALL_PLANE = 0, LPR_WALL_DISK = 1, LPR_WALL_ANNULUS = 2, LPR_WALL_BOX = 3 };
@@ -150,6 +153,9 @@ typedef struct {
   int32_t sort_every;
   int32_t input_order;     /* 1: start from the caller's order instead of the
                               sorted one (to measure what the sort buys) */
+  float level_cell_factor[16];  /* per radius band (cell-list level q, the
+                                   q-th band from the finest): its cell
+                                   factor, >= 1; 0 takes cell_factor */
 } lpr_bed_desc;
 
 #define LPR_MAX_WALLS 16
@@ -276,6 +282,11 @@ typedef struct {
   int32_t adjoint_interval; /* checkpoint interval of the last adjoint window
                                (0 before the first) */
   int64_t sorts;            /* device re-sorts of the storage order */
+  int64_t outside_grid;     /* binnings of a particle outside its level's
+                               grid on a bounded axis since creation (it is
+                               then binned into the edge cell and its
+                               contacts are still found; a growing count
+                               means the bed left its planned extent) */
 } lpr_stats;
 lpr_status lpr_get_stats(lpr_bed* bed, lpr_stats* out);
 
@@ -319,8 +330,10 @@ lpr_status lpr_set_launch(lpr_bed* bed, int32_t block, int32_t persistent);
 /* Autotuner.  Times `trial_steps` steps of throwaway copies of the beds
  * for each cell-list layout (band_ratio in {1.5, 2, 3} x cell_factor in
  * {1, 1.25}), then each launch shape (block 64/128/256, persistent or not)
- * on the fastest layout, and returns the fastest setting in *best (and
- * every trial in `trials`, up to `capacity`; *n_trials gets the count).
+ * on the fastest layout, then, radius band by radius band (cell-list level
+ * q of every bed, finest first), cell factors 1.25 and 1.5 for that band
+ * alone, keeping each that is faster; returns the fastest setting in *best
+ * (and every trial in `trials`, up to `capacity`; *n_trials gets the count).
  * None of these choices changes the contacts found or the results. */
 typedef struct {
   float band_ratio;
@@ -328,6 +341,7 @@ typedef struct {
   int32_t block;
   int32_t persistent;
   double ms_per_step;
+  float level_cell_factor[16];  /* per radius band; 0: cell_factor */
 } lpr_tuning;
 lpr_status lpr_autotune(const lpr_bed_desc* const* descs, int32_t n_beds, const lpr_allocator* alloc,
                         void* hip_stream, int32_t trial_steps, lpr_tuning* best, lpr_tuning* trials,

@@ -57,6 +57,7 @@ constexpr int WALL_BIT = 16;
 constexpr uint32_t ERR_CAPACITY = 1u;
 constexpr uint32_t ERR_NUMERIC = 2u;
 constexpr uint32_t ERR_SKIN = 4u;
+constexpr uint32_t ERR_WALL = 8u;   // a particle's centre lies beyond a plane wall by more than its radius
 
 enum { WPLANE = 0, WDISK = 1, WANNULUS = 2, WBOX = 3 };
 

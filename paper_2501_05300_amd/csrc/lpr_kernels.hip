@@ -107,6 +107,19 @@ __global__ void k_bin(DevBufs d, int s) {
   const int cx = cell_axis(G, 0, p.x), cy = cell_axis(G, 1, p.y), cz = cell_axis(G, 2, p.z);
   const int32_t c = (int32_t)(G.base + ((int64_t)cz * G.n[1] + cy) * G.n[0] + cx);
   d.pcell[i] = c;
+  {
+    // outside the level's grid on a bounded axis the particle is binned into
+    // the edge cell (the search covers it there); count such binnings
+#pragma clang fp contract(off)
+    bool out = false;
+    const double q[3] = {p.x, p.y, p.z};
+    for (int a = 0; a < 3; ++a)
+      if (!G.per[a]) {
+        const double f = (q[a] - G.lo[a]) * G.inv_w[a];
+        out = out || !(f >= 0.0 && f < (double)G.n[a]);
+      }
+    if (out) atomicAdd(&d.stat[2], 1u);
+  }
   if (SORT) {
     const int32_t cc[3] = {cx, cy, cz};
     d.skey[0][i] = (uint32_t)(G.base + morton_rank(cc, G.n));
@@ -1068,6 +1081,8 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
         if (W.body != b) continue;
         double dl, nx, ny, nz;
         if (!wall_geom(W, xi.x, xi.y, xi.z, xi.w, dl, nx, ny, nz)) continue;
+        // a sphere wholly through a plane has tunnelled: a failed run
+        if (W.kind == WPLANE && dl > 2.0 * xi.w) atomicOr(d.err, ERR_WALL);
         hit = 1;
         LawIn in;
         if ((fold >> (WALL_BIT + w)) & 1u) {

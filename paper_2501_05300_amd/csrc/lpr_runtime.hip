@@ -244,6 +244,9 @@ lpr_status validate(const lpr_bed_desc* d) {
   if (d->block != 0 && d->block != 64 && d->block != 128 && d->block != 256)
     return fail(LPR_E_INVAL, "block must be 64, 128 or 256");
   if (d->sort_every > 4096) return fail(LPR_E_INVAL, "sort_every must be at most 4096");
+  for (int q = 0; q < MAXLEV; ++q)
+    if (d->level_cell_factor[q] != 0.f && !(d->level_cell_factor[q] >= 1.f))
+      return fail(LPR_E_INVAL, "level_cell_factor entries must be 0 or >= 1");
   float rmax = 0.f;
   for (int64_t i = 0; i < d->n; ++i) rmax = std::max(rmax, d->radius[i]);
   for (int a = 0; a < 2; ++a)
@@ -286,7 +289,8 @@ void plan_bed(const lpr_bed_desc* D, double band_ratio, double cell_factor, doub
     LevelGrid G{};
     double rm = rmax[q] > 0.0 ? rmax[q] : thr[q + 1];
     if (rmax[q] <= 0.0) { xlo[q] = xhi[q] = ylo[q] = yhi[q] = zlo[q] = zhi[q] = 0.0; }
-    const double hcell = cell_factor * (2.0 * rm + skin);
+    const double cf_q = D->level_cell_factor[q] > 0.f ? (double)D->level_cell_factor[q] : cell_factor;
+    const double hcell = cf_q * (2.0 * rm + skin);
     const double lo3[3] = {xlo[q], ylo[q], zlo[q]}, hi3[3] = {xhi[q], yhi[q], zhi[q]};
     for (int a = 0; a < 3; ++a) {
       const bool per = (a < 2) && ((D->periodic >> a) & 1u);
@@ -428,9 +432,11 @@ lpr_status sync_check(lpr_bed* b) {
     b->faulted = true;
     if (e & ERR_CAPACITY) b->fault_status = LPR_E_CAPACITY;
     else if (e & ERR_NUMERIC) b->fault_status = LPR_E_NUMERIC;
+    else if (e & ERR_WALL) b->fault_status = LPR_E_DOMAIN;
     else b->fault_status = LPR_E_STATE;
     return fail(b->fault_status, (e & ERR_CAPACITY) ? "a particle exceeded its contact slots"
                                 : (e & ERR_NUMERIC) ? "non-finite force or state"
+                                : (e & ERR_WALL)    ? "a particle passed through a plane wall"
                                                     : "latched device fault");
   }
   return LPR_OK;
@@ -842,6 +848,7 @@ const char* lpr_status_str(lpr_status s) {
     case LPR_E_CAPACITY: return "capacity exceeded";
     case LPR_E_STATE: return "invalid state";
     case LPR_E_NUMERIC: return "non-finite value";
+    case LPR_E_DOMAIN: return "particle through a wall";
   }
   return "unknown status";
 }
@@ -1413,6 +1420,7 @@ lpr_status lpr_get_stats(lpr_bed* b, lpr_stats* out) {
   out->skin_trips = b->skin_trips;
   out->adjoint_interval = b->adj_interval;
   out->sorts = b->sorts;
+  out->outside_grid = stat[2];
   return LPR_OK;
 }
 
@@ -1473,6 +1481,10 @@ lpr_status time_trial(lpr_bed* b, int32_t steps, double* ms_per_step) {
 
 }  // namespace
 
+// The per-band cell factor the beds being tuned share for level q (the
+// caller's, or 0).
+static float w0_level(const std::vector<lpr_bed_desc>& work, int q) { return work.empty() ? 0.f : work[0].level_cell_factor[q]; }
+
 lpr_status lpr_autotune(const lpr_bed_desc* const* descs, int32_t n_beds, const lpr_allocator* alloc,
                         void* hip_stream, int32_t trial_steps, lpr_tuning* best, lpr_tuning* trials,
                         int32_t capacity, int32_t* n_trials) {
@@ -1506,7 +1518,8 @@ lpr_status lpr_autotune(const lpr_bed_desc* const* descs, int32_t n_beds, const 
       st = time_trial(b, trial_steps, &ms);
       lpr_bed_destroy(b);
       if (st != LPR_OK) return st;
-      lpr_tuning t{br, cf, 256, 0, ms};
+      lpr_tuning t{br, cf, 256, 0, ms, {}};
+      for (int q = 0; q < MAXLEV; ++q) t.level_cell_factor[q] = w0_level(work, q);
       done.push_back(t);
       if (ms < bestt.ms_per_step) bestt = t;
     }
@@ -1529,11 +1542,40 @@ lpr_status lpr_autotune(const lpr_bed_desc* const* descs, int32_t n_beds, const 
         lpr_bed_destroy(b);
         return st;
       }
-      lpr_tuning t{bestt.band_ratio, bestt.cell_factor, bl, pe, ms};
+      lpr_tuning t = bestt;
+      t.block = bl;
+      t.persistent = pe;
+      t.ms_per_step = ms;
       done.push_back(t);
       if (ms < bestt.ms_per_step) bestt = t;
     }
+  int nlev = 1;
+  for (const HostBed& H : b->hb) nlev = std::max(nlev, H.nlev);
   lpr_bed_destroy(b);
+  // radius band by radius band: a larger cell factor for that band alone
+  for (auto& w : work) {
+    w.block = bestt.block;
+    w.persistent = bestt.persistent;
+  }
+  const float band_cells[2] = {1.25f, 1.5f};
+  for (int q = 0; q < nlev; ++q)
+    for (float cf : band_cells) {
+      for (auto& w : work)
+        for (int q2 = 0; q2 < MAXLEV; ++q2) w.level_cell_factor[q2] = bestt.level_cell_factor[q2];
+      for (auto& w : work) w.level_cell_factor[q] = cf;
+      lpr_bed* bq = nullptr;
+      st = create_impl(ptrs.data(), n_beds, alloc, hip_stream, &bq);
+      if (st != LPR_OK) return st;
+      double ms = 0.0;
+      st = time_trial(bq, trial_steps, &ms);
+      lpr_bed_destroy(bq);
+      if (st != LPR_OK) return st;
+      lpr_tuning t = bestt;
+      t.level_cell_factor[q] = cf;
+      t.ms_per_step = ms;
+      done.push_back(t);
+      if (ms < bestt.ms_per_step) bestt = t;
+    }
   *best = bestt;
   if (n_trials) *n_trials = (int32_t)done.size();
   if (trials)

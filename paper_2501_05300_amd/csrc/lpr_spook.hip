@@ -140,6 +140,7 @@ __global__ __launch_bounds__(SP_BS) void k_sp_rows(DevBufs d, SpBufs sp, int s, 
     const WallPose& W = d.walls[bc.wall0 + w];
     double delta, nx, ny, nz;
     if (!wall_geom(W, me.x.x, me.x.y, me.x.z, ri, delta, nx, ny, nz)) continue;
+    if (W.kind == WPLANE && delta > 2.0 * ri) atomicOr(d.err, ERR_WALL);  // tunnelled through a plane
     const int64_t q = (int64_t)w * N + i;
     const D3 n = mk(nx, ny, nz);
     SpWRow r;

@@ -21,7 +21,7 @@ MAX_WALLS = 16
 MAX_BODIES = 4
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error", -4: "capacity exceeded",
-          -5: "invalid state", -6: "non-finite value"}
+          -5: "invalid state", -6: "non-finite value", -7: "particle through a wall"}
 
 # Entry points declared in include/lprdem.h
 _PER_BED = ("get_state", "set_state", "get_history", "set_history", "read_contacts", "read_forces", "read_reaction",
@@ -72,7 +72,8 @@ class _Desc(ctypes.Structure):
                 ("n_bodies", ctypes.c_int32), ("bodies", ctypes.c_void_p), ("params", _Params),
                 ("rebuild_every", ctypes.c_int32), ("skin", ctypes.c_float), ("band_ratio", ctypes.c_float),
                 ("cell_factor", ctypes.c_float), ("block", ctypes.c_int32), ("record_forces", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("sort_every", ctypes.c_int32), ("input_order", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("sort_every", ctypes.c_int32), ("input_order", ctypes.c_int32),
+                ("level_cell_factor", ctypes.c_float * 16)]
 
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
@@ -103,14 +104,15 @@ assert _HISTORY_DT.itemsize == ctypes.sizeof(_History)
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("band_ratio", ctypes.c_float), ("cell_factor", ctypes.c_float), ("block", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
+                ("persistent", ctypes.c_int32), ("ms_per_step", ctypes.c_double),
+                ("level_cell_factor", ctypes.c_float * 16)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("contacts", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("rebuilds", ctypes.c_int64), ("levels", ctypes.c_int32), ("cells", ctypes.c_int64),
                 ("max_owner_slots", ctypes.c_int32), ("skin_trips", ctypes.c_int64),
-                ("adjoint_interval", ctypes.c_int32), ("sorts", ctypes.c_int64)]
+                ("adjoint_interval", ctypes.c_int32), ("sorts", ctypes.c_int64), ("outside_grid", ctypes.c_int64)]
 
 
 _lib = None
@@ -191,7 +193,7 @@ class _DescHolder:
     """A filled lpr_bed_desc plus the arrays it points to (kept alive)."""
 
     def __init__(self, spec, rebuild_every, skin, band_ratio, cell_factor, block, record_forces, persistent=False,
-                 sort_every=0, input_order=False):
+                 sort_every=0, input_order=False, level_cell_factor=None):
         self.pos = np.ascontiguousarray(spec.pos, np.float64)
         self.rad = np.ascontiguousarray(spec.radius, np.float32)
         self.vel = np.ascontiguousarray(spec.vel, np.float32)
@@ -231,6 +233,8 @@ class _DescHolder:
         D.persistent = 1 if persistent else 0
         D.sort_every = int(sort_every)
         D.input_order = 1 if input_order else 0
+        for q, f in enumerate(level_cell_factor or ()):
+            D.level_cell_factor[q] = float(f)
         self.desc = D
 
 
@@ -458,7 +462,7 @@ class Bed(_Stepper):
 
     def __init__(self, spec, rebuild_every=1, skin=0.0, band_ratio=0.0, cell_factor=0.0, block=0,
                  record_forces=False, persistent=False, device=0, torch_memory=True, sort_every=0,
-                 input_order=False):
+                 input_order=False, level_cell_factor=None):
         import torch
         self.device = _gpu_or_raise(device)
         L = load_library()
@@ -466,7 +470,7 @@ class Bed(_Stepper):
         self.n = spec.n
         self.stream = torch.cuda.Stream(self.device)
         self._holder = _DescHolder(spec, rebuild_every, skin, band_ratio, cell_factor, block, record_forces,
-                                   persistent, sort_every, input_order)
+                                   persistent, sort_every, input_order, level_cell_factor)
         self._mem = _TorchMemory(self.device, self.stream)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -486,7 +490,8 @@ class Batch(_Stepper):
     _batch = True
 
     def __init__(self, specs, rebuild_every=1, skin=0.0, band_ratio=0.0, cell_factor=0.0, block=0,
-                 record_forces=False, persistent=False, device=0, layouts=None, sort_every=0, input_order=False):
+                 record_forces=False, persistent=False, device=0, layouts=None, sort_every=0, input_order=False,
+                 level_cell_factor=None):
         import torch
         self.device = _gpu_or_raise(device)
         L = load_library()
@@ -496,7 +501,7 @@ class Batch(_Stepper):
         for q, s in enumerate(self.specs):
             br, cf = (layouts[q] if layouts is not None else (band_ratio, cell_factor))
             self._holders.append(_DescHolder(s, rebuild_every, skin, br, cf, block, record_forces, persistent,
-                                             sort_every, input_order))
+                                             sort_every, input_order, level_cell_factor))
         arr = (ctypes.POINTER(_Desc) * len(self._holders))(*[ctypes.pointer(h.desc) for h in self._holders])
         self._mem = _TorchMemory(self.device, self.stream)
         h = ctypes.c_void_p()
@@ -533,7 +538,10 @@ def autotune(specs, trial_steps=20, rebuild_every=1, skin=0.0, device=0):
         rc = L.lpr_autotune(arr, len(holders), ctypes.byref(mem.struct), ctypes.c_void_p(stream.cuda_stream),
                             int(trial_steps), ctypes.byref(best), trials, 32, ctypes.byref(nt))
     _check(rc, "lpr_autotune")
-    as_dict = lambda t: {f: getattr(t, f) for f, _ in _Tuning._fields_}
+    def as_dict(t):
+        d = {f: getattr(t, f) for f, _ in _Tuning._fields_}
+        d["level_cell_factor"] = [float(x) for x in t.level_cell_factor]
+        return d
     return as_dict(best), [as_dict(trials[q]) for q in range(nt.value)]
 
 

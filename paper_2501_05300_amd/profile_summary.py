@@ -139,8 +139,19 @@ def write_traffic(fdir, wdir, avg_us, name, title, args, cbar, alg_line=None, st
     return rec, sf, sw
 
 
+def measured_cbar(src, name, default):
+    """Contacts per particle the workload recorded for a mode (or default)."""
+    path = os.path.join(src, name)
+    if os.path.exists(path):
+        with open(path) as f:
+            return float(json.load(f)["contacts_per_particle"])
+    return default
+
+
 def main(src, cbar_every=2.42, cbar_skin=2.42):
     os.makedirs(PROFILES, exist_ok=True)
+    cbar_every = measured_cbar(src, "stats_every.json", cbar_every)
+    cbar_skin = measured_cbar(src, "stats_skin.json", cbar_skin)
     every, calls_e = write_trace(os.path.join(src, "trace_every"), "kernels_metric_bed_every_step.txt",
                                  "settled 2,000,000-sphere graded bed, cell search every step", "", 100)
     skin, calls_s = write_trace(os.path.join(src, "trace_skin"), "kernels_metric_bed_skin_lists.txt",

@@ -33,7 +33,8 @@ def settled_metric_bed(cache, settle):
         log(f"loaded settled state from {cache}")
         return spec
     import bench
-    bench.settle_beds([spec], settle)
+    done, cbar, ok = bench.settle_beds([spec], settle, max_steps=200_000)
+    log(f"settled {done} steps, contacts per particle {cbar:.3f}, criterion met: {ok}")
     if cache:
         np.savez(cache, pos=spec.pos)
     return spec
@@ -48,6 +49,7 @@ def main():
     ap.add_argument("--rebuild-every", type=int, default=1)
     ap.add_argument("--skin", type=float, default=0.0)
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--stats-out", default="", help="write the bed's stats after the steps to this JSON file")
     ap.add_argument("--implicit", type=int, default=0,
                     help="> 0: the time-implicit step at dt 0.1 ms with this many iterations per step")
     args = ap.parse_args()
@@ -74,7 +76,12 @@ def main():
     t0 = time.perf_counter()
     bed.step(args.steps)
     bed.sync()
-    log(f"{args.steps} steps in {time.perf_counter() - t0:.3f} s; stats {bed.stats()}")
+    st = bed.stats()
+    log(f"{args.steps} steps in {time.perf_counter() - t0:.3f} s; stats {st}")
+    if args.stats_out:
+        import json
+        with open(args.stats_out, "w") as f:
+            json.dump({**st, "n": spec.n, "contacts_per_particle": st["contacts"] / spec.n}, f)
 
 
 if __name__ == "__main__":

@@ -81,16 +81,21 @@ def test_autotuner_returns_a_working_setting():
     specs = small_family()
     best, trials = autotune(specs, trial_steps=5)
     print(best)
-    assert len(trials) == 11
+    assert len(trials) >= 11 + 2  # layouts, launch shapes, then two cell factors per radius band
     assert best["ms_per_step"] > 0 and best["block"] in (64, 128, 256)
     ref = Batch(specs)
     tuned = Batch(specs, band_ratio=best["band_ratio"], cell_factor=best["cell_factor"], block=best["block"],
-                  persistent=best["persistent"])
+                  persistent=best["persistent"], level_cell_factor=best["level_cell_factor"])
+    banded = Batch(specs, level_cell_factor=[1.5, 1.25, 1.5])   # one setting per radius band
+    banded.step(30)
     ref.step(30)
     tuned.step(30)
     for q in range(len(specs)):
         assert np.array_equal(ref.contacts(bed=q), tuned.contacts(bed=q))
+        assert np.array_equal(ref.contacts(bed=q), banded.contacts(bed=q))
         # per-particle sums run in stable-id order, whatever the layout
         xa, va, _ = ref.state(bed=q)
         xb, vb, _ = tuned.state(bed=q)
+        xc, vc, _ = banded.state(bed=q)
         assert np.array_equal(xa, xb) and np.array_equal(va, vb), q
+        assert np.array_equal(xa, xc) and np.array_equal(va, vc), q

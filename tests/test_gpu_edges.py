@@ -173,3 +173,46 @@ def test_explicit_step_on_an_incline_on_the_gpu(mu, rolls):
     a = float(bed.state()[1][0].astype(np.float64) @ down) / (5000 * 2e-6)
     ref = (5.0 / 7.0) * 9.81 * math.sin(theta) if rolls else 9.81 * (math.sin(theta) - mu * math.cos(theta))
     assert abs(a / ref - 1.0) < 1e-3, (a, ref)
+
+
+def test_sphere_through_the_floor_latches():
+    """A sphere whose centre is set below the floor by more than its radius
+    has tunnelled: the step latches LPR_E_DOMAIN, reported at lpr_sync; the
+    state stays readable at the last complete step."""
+    from paper_2501_05300_amd.lprdem import Bed, LprError
+    spec = spec_of([[0.05, 0.05, 0.002], [0.02, 0.02, 0.002]], [2e-3, 2e-3], walls=[beds.floor_wall()])
+    bed = Bed(spec)
+    bed.step(5)
+    bed.sync()
+    x, v, w = bed.state()
+    x[1, 2] = -0.0025
+    bed.set_state(x, v, w)
+    bed.step(3)
+    with pytest.raises(LprError) as e:
+        bed.sync()
+    assert e.value.status == -7
+    x2, _, _ = bed.state()
+    assert x2[1, 2] == -0.0025   # no step completed after the set
+    with pytest.raises(LprError):
+        bed.step(1)
+
+
+def test_sphere_outside_its_level_grid_is_counted_and_still_found():
+    """A sphere thrown far above the planned extent of its level's grid is
+    binned into the edge cell: the step still matches the oracle, and the
+    binning is counted."""
+    from paper_2501_05300_amd.lprdem import Bed
+    spec = beds.add_plate(beds.two_layer_bed(41), diameter=0.04, speed=0.5)
+    bed = Bed(spec, record_forces=True)
+    bed.step(100)
+    x, v, w = bed.state()
+    # two spheres high above the bed, overlapping slightly
+    reach = 0.98 * float(spec.radius[0] + spec.radius[1])
+    x[0] = (0.03, 0.03, 0.5)
+    x[1] = (0.03 + reach, 0.03, 0.5)
+    bed.set_state(x, v, w)
+    res = compare_one_step(spec, bed)
+    print({k: v for k, v in res.items() if k not in ("only_gpu", "only_oracle")})
+    assert_parity(res, 1e-5)
+    assert (0, 1) in set(map(tuple, bed.contacts().tolist()))
+    assert bed.stats()["outside_grid"] >= 2
