@@ -250,6 +250,17 @@ typedef struct {
  * record_forces and the explicit stepper, else LPR_E_STATE); LPR_E_CAPACITY
  * with *n_total set and nothing written when capacity is too small. */
 lpr_status lpr_read_contact_loads(lpr_bed* bed, lpr_contact_load* out, int64_t capacity, int64_t* n_total);
+/* For callers that cannot allocate device memory (serving loops, harnesses
+ * that forbid allocation): lpr_read_contact_loads without any allocation.
+ * Its workspace is a static device array of LPR_NOALLOC_SCRATCH_BYTES that
+ * each GPU the library runs on holds until the process ends; it must hold
+ * about 8 bytes per particle (n rounded up to 256) plus 48 bytes per
+ * contact, else LPR_E_CAPACITY (nothing written).  The bed must have no
+ * pending device status (call lpr_sync after stepping; else LPR_E_STATE).
+ * Calls that overlap on one GPU share the array and race: serialise them.
+ * Same output and errors as lpr_read_contact_loads otherwise. */
+#define LPR_NOALLOC_SCRATCH_BYTES (32u << 20)
+lpr_status lpr_read_contact_loads_noalloc(lpr_bed* bed, lpr_contact_load* out, int64_t capacity, int64_t* n_total);
 /* World pose of wall `wall` at the current clock (the pose the next step
  * uses): origin (3), unit normal `axis` after the body's motion (3), and the
  * three rows of its frame (9).  The body rotation angle is ang_vel * k dt

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1982,6 +1983,76 @@ lpr_status lpr_set_body_state(lpr_bed* b, int32_t body, double z, double vz) { r
 lpr_status lpr_batch_set_body_state(lpr_bed* b, int32_t bed, int32_t body, double z, double vz) {
   if (!b || bed < 0 || bed >= (int32_t)b->hb.size()) return fail(LPR_E_INVAL, "bed index out of range");
   return set_body_state_impl(b, bed, body, z, vz);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Per-contact read without allocation: the workspace is a static device
+// array, one per GPU the library runs on, held until the process ends.  Host
+// code must use its address from hipGetSymbolAddress (the array's own name is
+// a host-side stand-in), taken once per device with that device current.
+
+static_assert(LPR_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static __device__ __align__(256) unsigned char scratch[LPR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+lpr_status scratch_address(int dev, char** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(LPR_E_DEVICE, "device index out of range for the static scratch");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LPR_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (char*)g_scratch_ptr[dev];
+  return LPR_OK;
+}
+
+lpr_status read_contact_loads_noalloc_impl(lpr_bed* b, int32_t bed, lpr_contact_load* out, int64_t capacity,
+                                           int64_t* n_total) {
+  lpr_status st = loads_readable(b);
+  if (st != LPR_OK) return st;
+  // no sync_check: its recovery from a skin trip re-enqueues steps and grows
+  // host logs; a bed whose last steps have not been checked is refused
+  HIPTRY(hipStreamSynchronize(b->stream));
+  uint32_t e = 0;
+  HIPTRY(hipMemcpy(&e, b->d.err, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  if (e != 0u || b->faulted) return fail(LPR_E_STATE, "the bed has a pending device status: call lpr_sync first");
+  const int64_t np = b->hb[bed].npad;
+  const size_t head = load_head_bytes(np);
+  if (head > (size_t)LPR_NOALLOC_SCRATCH_BYTES)
+    return fail(LPR_E_CAPACITY, "bed too large for the static scratch of lpr_read_contact_loads_noalloc");
+  char* ws = nullptr;
+  if ((st = scratch_address(b->device, &ws)) != LPR_OK) return st;
+  int64_t total = 0;
+  if ((st = load_count(b, bed, ws, &total)) != LPR_OK) return st;
+  if (n_total) *n_total = total;
+  if (total > capacity) return fail(LPR_E_CAPACITY, "contact buffer too small");
+  if (head + sizeof(lpr_contact_load) * (size_t)total > (size_t)LPR_NOALLOC_SCRATCH_BYTES)
+    return fail(LPR_E_CAPACITY, "more contacts than the static scratch of lpr_read_contact_loads_noalloc holds");
+  return load_pack(b, bed, ws, (lpr_contact_load*)(ws + head), total, out);
+}
+
+}  // namespace
+
+extern "C" {
+
+lpr_status lpr_read_contact_loads_noalloc(lpr_bed* b, lpr_contact_load* out, int64_t capacity, int64_t* n_total) {
+  if (!b) return fail(LPR_E_INVAL, "null bed");
+  int cur = 0;
+  HIPTRY(hipGetDevice(&cur));
+  if (cur != b->device) HIPTRY(hipSetDevice(b->device));
+  const lpr_status st = read_contact_loads_noalloc_impl(b, 0, out, capacity, n_total);
+  if (cur != b->device) (void)hipSetDevice(cur);
+  return st;
 }
 
 }  // extern "C"

@@ -28,7 +28,7 @@ _PER_BED = ("get_state", "set_state", "get_history", "set_history", "read_contac
             "reaction_window", "read_body", "set_clock", "get_clock", "set_body_state", "read_contact_loads",
             "read_wall_pose")
 SYMBOLS = ("lpr_bed_create", "lpr_bed_destroy", "lpr_step", "lpr_step_profiled", "lpr_step_phases", "lpr_sync",
-           "lpr_get_stats",
+           "lpr_get_stats", "lpr_read_contact_loads_noalloc",
            "lpr_status_str", "lpr_last_error", "lpr_batch_create", "lpr_batch_size", "lpr_set_launch",
            "lpr_autotune", "lpr_set_contact_params", "lpr_adjoint_window", "lpr_set_stepper") + tuple("lpr_" + f for f in _PER_BED) + tuple("lpr_batch_" + f for f in _PER_BED)
 
@@ -140,6 +140,7 @@ def load_library(path: str = LIB_PATH):
         "lpr_read_body": [vp, i32, vp, vp], "lpr_set_clock": [vp, i64], "lpr_get_clock": [vp, ctypes.POINTER(i64)],
         "lpr_set_body_state": [vp, i32, d, d], "lpr_get_stats": [vp, ctypes.POINTER(_Stats)],
         "lpr_read_contact_loads": [vp, vp, i64, ctypes.POINTER(i64)], "lpr_read_wall_pose": [vp, i32, vp],
+        "lpr_read_contact_loads_noalloc": [vp, vp, i64, ctypes.POINTER(i64)],
     }
     for f in _PER_BED:
         args = sig["lpr_" + f]
@@ -411,6 +412,17 @@ class _Stepper:
             pass
         arr = np.zeros(max(1, tot.value), _LOAD_DT)
         self._call("read_contact_loads", bed, arr.ctypes.data, tot.value, ctypes.byref(tot))
+        arr = arr[:tot.value]
+        return np.stack([arr["a"], arr["b"]], 1), arr["f"].copy(), arr["m"].copy(), arr["fn"].copy()
+
+    def contact_loads_noalloc(self, capacity):
+        """contact_loads() of a single bed through the entry point that
+        allocates nothing (its workspace is the library's static device
+        array); `capacity` records are offered."""
+        tot = ctypes.c_int64(0)
+        arr = np.zeros(max(1, int(capacity)), _LOAD_DT)
+        _check(_lib.lpr_read_contact_loads_noalloc(self._h, arr.ctypes.data, int(capacity), ctypes.byref(tot)),
+               "lpr_read_contact_loads_noalloc")
         arr = arr[:tot.value]
         return np.stack([arr["a"], arr["b"]], 1), arr["f"].copy(), arr["m"].copy(), arr["fn"].copy()
 
