@@ -140,27 +140,30 @@ struct BedDyn {
 // code that is set, the cells sharing the code above that bit and having 0
 // there are counted axis by axis: each axis then has some high bits fixed and
 // its low bits free, and the count is the part of that range inside the grid.
-__host__ __device__ inline int64_t morton_rank(const int32_t c[3], const int32_t n[3]) {
-  const int32_t m = n[0] > n[1] ? (n[0] > n[2] ? n[0] : n[2]) : (n[1] > n[2] ? n[1] : n[2]);
+// Every count is at most the grid's cell total (< 2^31), so 32-bit
+// arithmetic is exact; the terms are formed for every bit and kept or not
+// without branching.
+__host__ __device__ inline uint32_t morton_rank(const int32_t c[3], const int32_t n[3]) {
+  const uint32_t m = (uint32_t)(n[0] > n[1] ? (n[0] > n[2] ? n[0] : n[2]) : (n[1] > n[2] ? n[1] : n[2]));
   int nb = 0;
-  while ((1 << nb) < m) ++nb;
-  int64_t rank = 0;
+  while ((1u << nb) < m) ++nb;
+  const uint32_t cx[3] = {(uint32_t)c[0], (uint32_t)c[1], (uint32_t)c[2]};
+  const uint32_t nx[3] = {(uint32_t)n[0], (uint32_t)n[1], (uint32_t)n[2]};
+  uint32_t rank = 0;
   for (int k = nb - 1; k >= 0; --k)
     for (int a = 2; a >= 0; --a) {
-      if (!((c[a] >> k) & 1)) continue;
-      int64_t prod = 1;
+      uint32_t prod = 1;
       for (int b = 0; b < 3; ++b) {
         // axes below a keep bit k free, axes above it have it fixed, axis a
         // has it fixed to 0
         const int sh = (b > a) ? k : k + 1;
         const int w = (b < a) ? k + 1 : k;
-        const int64_t lo = (int64_t)(c[b] >> sh) << sh;
-        int64_t cnt = (int64_t)n[b] - lo;
-        const int64_t cap = (int64_t)1 << w;
-        cnt = cnt < 0 ? 0 : (cnt > cap ? cap : cnt);
-        prod *= cnt;
+        const uint32_t lo = (cx[b] >> sh) << sh;
+        const uint32_t cnt = nx[b] > lo ? nx[b] - lo : 0u;
+        const uint32_t cap = 1u << w;
+        prod *= cnt < cap ? cnt : cap;
       }
-      rank += prod;
+      rank += ((cx[a] >> k) & 1u) ? prod : 0u;
     }
   return rank;
 }

@@ -1482,9 +1482,11 @@ lpr_status time_trial(lpr_bed* b, int32_t steps, double* ms_per_step) {
 
 }  // namespace
 
-// The per-band cell factor the beds being tuned share for level q (the
-// caller's, or 0).
-static float w0_level(const std::vector<lpr_bed_desc>& work, int q) { return work.empty() ? 0.f : work[0].level_cell_factor[q]; }
+// The per-band cell factor of level q in the descriptions being tuned (the
+// first bed's; the caller's choice, usually 0).
+static float given_level_factor(const std::vector<lpr_bed_desc>& work, int q) {
+  return work.empty() ? 0.f : work[0].level_cell_factor[q];
+}
 
 lpr_status lpr_autotune(const lpr_bed_desc* const* descs, int32_t n_beds, const lpr_allocator* alloc,
                         void* hip_stream, int32_t trial_steps, lpr_tuning* best, lpr_tuning* trials,
@@ -1520,7 +1522,7 @@ lpr_status lpr_autotune(const lpr_bed_desc* const* descs, int32_t n_beds, const 
       lpr_bed_destroy(b);
       if (st != LPR_OK) return st;
       lpr_tuning t{br, cf, 256, 0, ms, {}};
-      for (int q = 0; q < MAXLEV; ++q) t.level_cell_factor[q] = w0_level(work, q);
+      for (int q = 0; q < MAXLEV; ++q) t.level_cell_factor[q] = given_level_factor(work, q);
       done.push_back(t);
       if (ms < bestt.ms_per_step) bestt = t;
     }
