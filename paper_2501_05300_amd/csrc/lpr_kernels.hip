@@ -659,7 +659,11 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
     d.cflag[hn][i] = 0u;
     return;
   }
-  const BedConst bc = d.beds[m >> 8];
+  // a wave holds particles of one bed (beds are padded to PAD particles, a
+  // multiple of the wave size), so the bed's constants and level grids are
+  // read once per wave, as scalars
+  const int bed = __builtin_amdgcn_readfirstlane((int)(m >> 8));
+  const BedConst bc = d.beds[bed];
   const int lev_i = (int)(m & 0xffu);
   const double4 pi = d.st[s][i].x;
   // the previous lists' flags and count, read now so that their latency
@@ -680,32 +684,41 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
   const float mag = fmaxf(fmaxf(fabsf(pfx), fabsf(pfy)), fmaxf(fabsf(pfz), fmaxf(Lx, Ly)));
   const float reach = rif + bc.skin + mag * 0x1p-19f;
   int np = 0;
-  for (int lev = lev_i; lev < bc.nlev && np <= PCAP; ++lev) {
+  // levels in a loop that is the same for the whole wave (so each level's
+  // grid is a scalar read); a lane takes part from its own level on, in the
+  // coarser ones when their centres are within reach, and while its kept
+  // list has room
+  for (int lev = 0; lev < bc.nlev; ++lev) {
     const int gl = bc.lev0 + lev;
     const LevelGrid G = d.levels[gl];
-    if (lev > lev_i && !level_in_reach(d, gl, pi, pi.w + G.rmax + skin)) continue;
+    const double rch = pi.w + G.rmax + skin;
+    const bool want = lev >= lev_i && np <= PCAP && (lev == lev_i || level_in_reach(d, gl, pi, rch));
+    if (!__any(want)) continue;
     int nr = 0;
     bool wide = false;
     RowSet R;
-    row_set(G, pi, pi.w + G.rmax + skin, R);
+    R.across = false;
+    if (want) {
+      row_set(G, pi, rch, R);
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {  // compile-time piece index (registers, not scratch)
-      if (p >= R.nxp) break;
-      uint32_t q0[9], q1[9];
-      row_piece(d, G, R, p, q0, q1);
+      for (int p = 0; p < 2; ++p) {  // compile-time piece index (registers, not scratch)
+        if (p >= R.nxp) break;
+        uint32_t q0[9], q1[9];
+        row_piece(d, G, R, p, q0, q1);
 #pragma unroll
-      for (int r = 0; r < 9; ++r) {
-        const uint32_t len = q1[r] - q0[r];
-        if (len > 0u) {
-          wide = wide || len > 63u || q0[r] >= (1u << 26);
-          rtab[nr][t] = (q0[r] << 6) | (len & 63u);
-          ++nr;
+        for (int r = 0; r < 9; ++r) {
+          const uint32_t len = q1[r] - q0[r];
+          if (len > 0u) {
+            wide = wide || len > 63u || q0[r] >= (1u << 26);
+            rtab[nr][t] = (q0[r] << 6) | (len & 63u);
+            ++nr;
+          }
         }
       }
     }
     if (wide) {  // a row too long (or a list too large) for the packed table
       np = PCAP + 1;
-      break;
+      nr = 0;
     }
     if (__any(R.across))
       walk_rows<true>(d.cpf, rtab, c_idx, t, nr, pfx, pfy, pfz, rif, reach, perx, pery, Lx, Ly, np);
