@@ -407,7 +407,7 @@ constexpr int SBS = 64;   // threads per search block
 //   list and row LROWS - 1 a sink for the writes that keep nothing;
 //   exact walk (kept list full): rows [LROWS - K, LROWS) its partners;
 //   accepted partners: positions compacted in place in the kept rows, stable
-//   ids in rows [0, K) for the slot sort.
+//   ids in rows [0, K) for the slot sort, then each slot's previous slot.
 constexpr int LROWS = 32;
 constexpr int RT = 18;             // a level has at most 9 rows in each of two x pieces
 constexpr int PCAP = LROWS - RT - 1;  // first-pass candidates kept per particle (more: exact walk)
@@ -647,7 +647,10 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
   if (blk < 0) return;
   const int64_t i = blk * SBS + t;
   if (i >= d.N || latched(d.err)) return;
-  const int ln = lo ^ 1, hn = ho ^ 1;
+  // after a re-sort of the storage order (src given) the lists and springs
+  // are written to the other buffers; otherwise they are updated in place
+  const bool moved = src != nullptr;
+  const int ln = moved ? lo ^ 1 : lo, hn = moved ? ho ^ 1 : ho;
   const int64_t N = d.N;
   if (i == 0) {  // fresh lists: no displacement since they were built
     d.viol[0] = 0u;
@@ -668,7 +671,7 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
   const double4 pi = d.st[s][i].x;
   // the previous lists' flags and count, read now so that their latency
   // hides behind the walk
-  const int64_t io = src ? (int64_t)src[i] : i;
+  const int64_t io = moved ? (int64_t)src[i] : i;
   const uint32_t fo = d.cflag[ho][io];
   const int cnt_old = d.own_cnt[lo][io];
   const float rif = (float)pi.w;
@@ -796,10 +799,9 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
     c_idx[b + 1][t] = kj;
   }
   // slots four at a time, with every read and atomic of a group in flight
-  // together: storage index of the partner, its reverse-list rank, the slot
-  // it held in the previous lists and that slot's spring history (a slot
-  // whose pair was not in contact holds zero history, so readers need not
-  // consult the contact flags)
+  // together: storage index of the partner, its reverse-list rank and the
+  // slot it held in the previous lists.  A slot whose pair was not in contact
+  // holds zero history, so readers need not consult the contact flags.
   uint32_t fn = fo & 0xffff0000u;
   for (int k0 = 0; k0 < cnt; k0 += 4) {
     int32_t jj[4];
@@ -810,7 +812,7 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
     for (int u = 0; u < 4; ++u) rk[u] = (k0 + u < cnt) ? atomicAdd(&d.rev_cnt[jj[u]], 1u) : 0u;
     int32_t jo[4];  // the partner's index in the previous lists
 #pragma unroll
-    for (int u = 0; u < 4; ++u) jo[u] = (src && k0 + u < cnt) ? src[jj[u]] : jj[u];
+    for (int u = 0; u < 4; ++u) jo[u] = (moved && k0 + u < cnt) ? src[jj[u]] : jj[u];
     int mk[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -818,31 +820,72 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
 #pragma unroll
       for (int k2 = K - 1; k2 >= 0; --k2)
         if (old_j[k2] == jo[u]) mk[u] = k2;
+      if (k0 + u < cnt && mk[u] >= 0 && ((fo >> mk[u]) & 1u)) fn |= 1u << (k0 + u);
     }
-    HRec hr[4];
+    if (moved) {
+      // new storage order: the lists and springs move to the other buffers
+      HRec hr[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      hr[u].t = make_float4(0.f, 0.f, 0.f, 0.f);
-      hr[u].r = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (mk[u] >= 0 && ((fo >> mk[u]) & 1u)) {
-        hr[u] = d.hist[ho][(int64_t)mk[u] * N + io];
-        fn |= 1u << (k0 + u);
+      for (int u = 0; u < 4; ++u) {
+        hr[u].t = make_float4(0.f, 0.f, 0.f, 0.f);
+        hr[u].r = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (mk[u] >= 0 && ((fo >> mk[u]) & 1u)) hr[u] = d.hist[ho][(int64_t)mk[u] * N + io];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (k0 + u < cnt) {
+          const int64_t o = (int64_t)(k0 + u) * N + i;
+          d.own_idx[ln][o] = jj[u];
+          d.own_rank[o] = rk[u];
+          d.hist[hn][o] = hr[u];
+        }
+    } else {
+      // same storage order: the lists are rewritten in place where a slot
+      // changed, and the previous slot of each is kept for the springs
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (k0 + u < cnt) {
+          const int64_t o = (int64_t)(k0 + u) * N + i;
+          if (mk[u] != k0 + u) d.own_idx[ln][o] = jj[u];
+          d.own_rank[o] = rk[u];
+          c_sid[k0 + u][t] = mk[u];
+        }
+    }
+  }
+  if (!moved) {
+    // springs in place: slot k takes the spring of its previous slot m (or
+    // zero).  Both lists ascend in partner id, so m grows with k: copies to
+    // a lower slot, taken in ascending order, and copies to a higher slot,
+    // in descending order, never read a slot already written, and zeros go
+    // last.  An unchanged slot (m == k) is not touched, nor is a slot that
+    // already holds zero (a previous slot out of contact).
+    HRec* const H = d.hist[ho];
+    for (int k = 0; k < cnt; ++k) {
+      const int m = c_sid[k][t];
+      if (m > k && ((fo >> m) & 1u)) H[(int64_t)k * N + i] = H[(int64_t)m * N + i];
+    }
+    for (int k = cnt - 1; k >= 0; --k) {
+      const int m = c_sid[k][t];
+      if (m >= 0 && m < k && ((fo >> m) & 1u)) H[(int64_t)k * N + i] = H[(int64_t)m * N + i];
+    }
+    for (int k = 0; k < cnt; ++k) {
+      const int m = c_sid[k][t];
+      const bool live = m >= 0 && ((fo >> m) & 1u);
+      const bool zero_now = k < cnt_old && !((fo >> k) & 1u);
+      if (m != k && !live && !zero_now) {
+        HRec z;
+        z.t = make_float4(0.f, 0.f, 0.f, 0.f);
+        z.r = make_float4(0.f, 0.f, 0.f, 0.f);
+        H[(int64_t)k * N + i] = z;
       }
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (k0 + u < cnt) {
-        const int64_t o = (int64_t)(k0 + u) * N + i;
-        d.own_idx[ln][o] = jj[u];
-        d.own_rank[o] = rk[u];
-        d.hist[hn][o] = hr[u];
+  } else {
+    for (int w = 0; w < bc.nwall; ++w)
+      if ((fo >> (WALL_BIT + w)) & 1u) {
+        d.wA[hn][w * N + i] = d.wA[ho][w * N + io];
+        d.wB[hn][w * N + i] = d.wB[ho][w * N + io];
       }
   }
-  for (int w = 0; w < bc.nwall; ++w)
-    if ((fo >> (WALL_BIT + w)) & 1u) {
-      d.wA[hn][w * N + i] = d.wA[ho][w * N + io];
-      d.wB[hn][w * N + i] = d.wB[ho][w * N + io];
-    }
   d.own_cnt[ln][i] = cnt;
   d.cflag[hn][i] = fn;
   d.disp[i] = 0.f;

@@ -370,11 +370,13 @@ void set_par(lpr_bed* b, const Par& p) {
 // the captured cycle, S: rebuilds per re-sort, 0 for none).
 void simulate_step(Par& p, int R, int S) {
   if (p.since >= R) {
-    p.l ^= 1;
-    p.h ^= 1;
     p.since = 0;
     if (S > 0) {
-      if (p.sc == 0) p.o ^= 1;
+      if (p.sc == 0) {  // a re-sorting rebuild writes the other buffers
+        p.o ^= 1;
+        p.l ^= 1;
+        p.h ^= 1;
+      }
       p.sc = (p.sc + 1) % S;
     }
   }
@@ -468,8 +470,10 @@ void enqueue_rebuild(lpr_bed* b) {
   mark(b, 3);
   launch_search(d, b->s, b->l, b->h, srt ? d.src : nullptr, b->stream);
   mark(b, 4);
-  b->l ^= 1;
-  b->h ^= 1;
+  if (srt) {  // lists and springs moved to the other buffers (else updated in place)
+    b->l ^= 1;
+    b->h ^= 1;
+  }
   launch_scan(d.rev_cnt, d.rev_start, d.scan_tmp, d.N, b->stream);
   launch_rev_scatter(d, b->l, b->stream);
   launch_rev_sort(d, b->stream);
