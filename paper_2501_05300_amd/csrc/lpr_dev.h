@@ -50,6 +50,7 @@ constexpr int MAXW = 16;         // walls per bed
 constexpr int MAXB = 4;          // bodies per bed
 constexpr int PAD = 256;         // per-bed particle range alignment
 constexpr int MAXLEV = 16;       // cell-list levels per bed
+constexpr int CPF_PAD = 8;       // readable entries past the end of the cell-ordered FP32 copy
 constexpr uint32_t INACTIVE = 0xffffffffu;
 constexpr int WALL_BIT = 16;
 
@@ -65,6 +66,7 @@ enum { WPLANE = 0, WDISK = 1, WANNULUS = 2, WBOX = 3 };
 struct LevelGrid {
   double lo[3];      // origin (0 on periodic axes)
   double inv_w[3];   // 1 / cell width
+  double w[3];       // cell width
   int32_t n[3];      // cells per axis
   int32_t per[3];    // axis wraps
   int64_t base;      // first global cell id

@@ -50,7 +50,7 @@ struct DevBufs {
   // scan scratch
   uint32_t* scan_tmp;
   CRec* crec;            // position, radius and stable id in cell-list order (rebuild)
-  float4* cpf;           // FP32 (x, y, z, r) in cell-list order (rebuild)
+  float4* cpf;           // FP32 (x, y, z, r) in cell-list order (rebuild), CPF_PAD entries past N
   uint32_t* zext;        // [levels][2] highest z and highest -z of the level's centres seen
                          // (order-preserving FP32 bits, 0 = none; monotone)
   // storage-order sort (radix sort of (level, Morton) keys)

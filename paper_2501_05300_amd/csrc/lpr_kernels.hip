@@ -17,6 +17,7 @@
 //               sides of a pair are bitwise opposite; FP64 reaction partials
 //   k_advance   ordered FP64 reduction of reactions, dynamic bodies, next
 //               wall poses, clock
+#include "lpr_cells.h"
 #include "lpr_kernels.h"
 
 namespace lpr {
@@ -38,19 +39,6 @@ void launch_zero(uint32_t* p, int64_t n, hipStream_t st) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
-}
-
-LPR_DEV_INLINE int cell_axis(const LevelGrid& G, int a, double x) {
-#pragma clang fp contract(off)
-  double f = (x - G.lo[a]) * G.inv_w[a];
-  f = fmin(fmax(f, -1.0), (double)G.n[a]);
-  int c = (int)floor(f);
-  if (G.per[a]) {
-    if (c >= G.n[a]) c -= G.n[a];
-    if (c < 0) c += G.n[a];
-  }
-  c = c < 0 ? 0 : (c >= G.n[a] ? G.n[a] - 1 : c);
-  return c;
 }
 
 // Work block handled by launch block b of a grid of g blocks: the blocks
@@ -413,103 +401,6 @@ constexpr int RT = 18;             // a level has at most 9 rows in each of two 
 constexpr int PCAP = LROWS - RT - 1;  // first-pass candidates kept per particle (more: exact walk)
 static_assert(RT >= K && LROWS - K >= K, "sort ids must not overlap a kept list");
 
-// Cells along axis a that can hold a partner closer than `reach` to the
-// coordinate x: the range [c + lo, c + hi] around the particle's cell c, with
-// lo, hi in {-1, 0, 1} (a cell is at least `reach` wide, so one neighbour on
-// either side is the most that is ever needed).  The bounds come from the
-// cell coordinate of x -+ reach with a slack of 1e-9 cell, far above the
-// rounding of the cell coordinates, so no cell that holds such a partner is
-// dropped.
-LPR_DEV_INLINE void axis_span(const LevelGrid& G, int a, double x, double reach, int& c, int& lo, int& hi) {
-#pragma clang fp contract(off)
-  const int n = G.n[a];
-  c = cell_axis(G, a, x);
-  const double dr = reach * G.inv_w[a] + 1e-9;
-  if (G.per[a]) {
-    // offsets from the cell coordinate as cell_axis clamps it, so they are
-    // relative to c
-    const double f = fmin(fmax((x - G.lo[a]) * G.inv_w[a], -1.0), (double)n);
-    const double fc = floor(f);
-    lo = (floor(f - dr) < fc) ? -1 : 0;
-    hi = (floor(f + dr) > fc) ? 1 : 0;
-    return;
-  }
-  // binning clamps a cell index to the grid, so the span's ends are clamped
-  // the same way (particles beyond an edge sit in the edge cell)
-  const double f = fmin(fmax((x - G.lo[a]) * G.inv_w[a], -1073741824.0), 1073741824.0);
-  const int a0 = min(max((int)floor(f - dr), 0), n - 1), b0 = min(max((int)floor(f + dr), 0), n - 1);
-  lo = max(a0, c - 1) - c;
-  hi = min(b0, c + 1) - c;
-}
-
-// The particle's neighbour rows at one level: rows along x of the needed
-// (y, z) cells (the cells of a row are consecutive in the cell order), each
-// in one piece, or two where the x range wraps.  Short periodic axes (three
-// cells or fewer) take every cell once.
-struct RowSet {
-  int y0, nyl;          // rows y0 .. y0 + nyl - 1 (wrapped on a periodic axis)
-  int z0, nzl;          // rows z0 .. z0 + nzl - 1
-  int xa0, xb0, xa1, xb1, nxp;  // x pieces [xa, xb)
-  bool across;  // a cell lies across a periodic edge from the particle (only
-                // then can a separation need the minimum image)
-};
-
-LPR_DEV_INLINE void row_set(const LevelGrid& G, const double4& pi, double reach, RowSet& R) {
-  int cx, xl, xh, cy, yl, yh, cz, zl, zh;
-  axis_span(G, 0, pi.x, reach, cx, xl, xh);
-  axis_span(G, 1, pi.y, reach, cy, yl, yh);
-  axis_span(G, 2, pi.z, reach, cz, zl, zh);
-  if (G.per[1] && G.n[1] <= 3) {
-    R.y0 = 0;
-    R.nyl = G.n[1];
-  } else {
-    R.y0 = cy + yl;
-    R.nyl = max(0, yh - yl + 1);
-  }
-  R.across = G.per[1] && (G.n[1] <= 3 || cy + yl < 0 || cy + yh >= G.n[1]);
-  R.z0 = cz + zl;  // z never wraps
-  R.nzl = max(0, zh - zl + 1);
-  const int n = G.n[0];
-  R.xa0 = R.xb0 = R.xa1 = R.xb1 = 0;
-  R.nxp = 0;
-  if (G.per[0] && n <= 3) {
-    R.xb0 = n;
-    R.nxp = 1;
-    R.across = true;
-  } else if (xh >= xl) {
-    const int a0 = cx + xl, b0 = cx + xh + 1;  // [a0, b0), may leave [0, n) on a periodic axis
-    if (a0 < 0) {
-      R.xa0 = 0; R.xb0 = b0; R.xa1 = a0 + n; R.xb1 = n; R.nxp = 2;
-      R.across = true;
-    } else if (b0 > n) {
-      R.xa0 = a0; R.xb0 = n; R.xa1 = 0; R.xb1 = b0 - n; R.nxp = 2;
-      R.across = true;
-    } else {
-      R.xa0 = a0; R.xb0 = b0; R.nxp = 1;
-    }
-  }
-}
-
-// Cell-list bounds [q0, q1) of the nine rows of x piece p (empty rows
-// [0, 0)).
-LPR_DEV_INLINE void row_piece(const DevBufs& d, const LevelGrid& G, const RowSet& R, int p, uint32_t q0[9],
-                              uint32_t q1[9]) {
-  const int xa = p ? R.xa1 : R.xa0, xb = p ? R.xb1 : R.xb0;
-#pragma unroll
-  for (int r = 0; r < 9; ++r) {
-    const int a = r / 3, b = r % 3;
-    q0[r] = 0u;
-    q1[r] = 0u;
-    if (a < R.nzl && b < R.nyl && p < R.nxp) {
-      int y = R.y0 + b;
-      if (G.per[1]) y = (y < 0) ? y + G.n[1] : (y >= G.n[1] ? y - G.n[1] : y);
-      const int64_t rb = G.base + ((int64_t)(R.z0 + a) * G.n[1] + y) * G.n[0];
-      q0[r] = d.cell_start[rb + xa];
-      q1[r] = d.cell_start[rb + xb];
-    }
-  }
-}
-
 // a if c, else b, as bit masks (a plain conditional here would be turned into
 // control flow)
 LPR_DEV_INLINE uint32_t pick(bool c, uint32_t a, uint32_t b) {
@@ -524,8 +415,21 @@ LPR_DEV_INLINE uint32_t pick(bool c, uint32_t a, uint32_t b) {
 // larger radius owns nothing here).  WRAP takes the minimum image on the
 // periodic axes; a wave whose lanes have no cell across a periodic edge
 // skips it, since then every separation is already the nearest image.
+// The FP32 copy is read through a buffer resource: 32-bit byte offsets (one
+// shift per address) and a hardware range check (reads past the resource
+// return zeros).  Word 3 is the data format field of CDNA buffer resources
+// for plain dword reads.
+LPR_DEV_INLINE __amdgpu_buffer_rsrc_t cand_rsrc(const float4* cpf, int64_t n) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)cpf, (short)0, (int)((n + CPF_PAD) * 16), 0x00020000);
+}
+
+LPR_DEV_INLINE float4 cand_load(__amdgpu_buffer_rsrc_t rs, uint32_t q) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(q << 4), 0, 0);
+  return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), __uint_as_float(v[3]));
+}
+
 template <bool WRAP>
-LPR_DEV_INLINE void walk_rows(const float4* __restrict__ cpf, const uint32_t (*rtab)[SBS], int32_t (*c_idx)[SBS], int t,
+LPR_DEV_INLINE void walk_rows(__amdgpu_buffer_rsrc_t cpf, const uint32_t (*rtab)[SBS], int32_t (*c_idx)[SBS], int t,
                               int nr, float pfx, float pfy, float pfz, float rif, float reach, bool perx, bool pery,
                               float Lx, float Ly, int& np) {
   if (nr <= 0) return;
@@ -544,21 +448,25 @@ LPR_DEV_INLINE void walk_rows(const float4* __restrict__ cpf, const uint32_t (*r
     float4 c[8];
     uint32_t qa[8];
     bool ok[8];
-    // positions of the round without branches: the rest of row ri, then
-    // rows ri + 1 and ri + 2 (a round ends early where it would need a
-    // fourth row)
+    // positions of the round: the rest of row ri, then rows ri + 1 and
+    // ri + 2 (a round ends early where it would need a fourth row).
+    // Position u lies in row A below sB (= avA), in row B below sC, else in
+    // row C, at u plus that row's offset.  Positions past the three rows
+    // (ok false) are read all the same: they lie within seven of a row's
+    // start, which the copy's padding covers, and are never kept.
     const int avA = (int)la;
     const int avB = (ri + 1 < nr) ? (int)(wb & 63u) : 0;
     const int avC = (ri + 2 < nr) ? (int)(wc & 63u) : 0;
-    const uint32_t qb0 = wb >> 6, qc0 = wc >> 6;
+    const uint32_t qb0 = (ri + 1 < nr) ? wb >> 6 : qa0, qc0 = (ri + 2 < nr) ? wc >> 6 : qa0;
+    const int sB = avA, sC = avA + avB, sE = sC + avC;
+    const uint32_t oB = qb0 - (uint32_t)sB, oC = qc0 - (uint32_t)sC;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int ub = u - avA, uc = ub - avB;
-      qa[u] = pick(u < avA, qa0 + (uint32_t)u, pick(ub < avB, qb0 + (uint32_t)ub, qc0 + (uint32_t)uc));
-      ok[u] = uc < avC;
+      qa[u] = (uint32_t)u + (u < sB ? qa0 : (u < sC ? oB : oC));
+      ok[u] = u < sE;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) c[u] = cpf[pick(ok[u], qa[u], qa0)];
+    for (int u = 0; u < 8; ++u) c[u] = cand_load(cpf, qa[u]);
     {
       // move past the rows this round used up (their LDS entries are read
       // while the candidates are in flight)
@@ -686,6 +594,7 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
   // 2^-19 of it is 16 ulp
   const float mag = fmaxf(fmaxf(fabsf(pfx), fabsf(pfy)), fmaxf(fabsf(pfz), fmaxf(Lx, Ly)));
   const float reach = rif + bc.skin + mag * 0x1p-19f;
+  const __amdgpu_buffer_rsrc_t crs = cand_rsrc(d.cpf, N);
   int np = 0;
   // levels in a loop that is the same for the whole wave (so each level's
   // grid is a scalar read); a lane takes part from its own level on, in the
@@ -707,7 +616,7 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
       for (int p = 0; p < 2; ++p) {  // compile-time piece index (registers, not scratch)
         if (p >= R.nxp) break;
         uint32_t q0[9], q1[9];
-        row_piece(d, G, R, p, q0, q1);
+        row_piece(d.cell_start, G, R, p, q0, q1);
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
           const uint32_t len = q1[r] - q0[r];
@@ -724,9 +633,9 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
       nr = 0;
     }
     if (__any(R.across))
-      walk_rows<true>(d.cpf, rtab, c_idx, t, nr, pfx, pfy, pfz, rif, reach, perx, pery, Lx, Ly, np);
+      walk_rows<true>(crs, rtab, c_idx, t, nr, pfx, pfy, pfz, rif, reach, perx, pery, Lx, Ly, np);
     else
-      walk_rows<false>(d.cpf, rtab, c_idx, t, nr, pfx, pfy, pfz, rif, reach, perx, pery, Lx, Ly, np);
+      walk_rows<false>(crs, rtab, c_idx, t, nr, pfx, pfy, pfz, rif, reach, perx, pery, Lx, Ly, np);
   }
   const bool exact = np > PCAP;
   if (exact) {
@@ -745,7 +654,7 @@ __global__ __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(5))) void k
       for (int p = 0; p < 2; ++p) {
         if (p >= R.nxp) break;
         uint32_t q0[9], q1[9];
-        row_piece(d, G, R, p, q0, q1);
+        row_piece(d.cell_start, G, R, p, q0, q1);
         for (int r = 0; r < 9; ++r)
           for (uint32_t q = q0[r]; q < q1[r]; ++q)
             if (owner_candidate(bc, pi, si, skin, d.crec[q])) {

@@ -16,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "lpr_cells.h"
 #include "lpr_kernels.h"
 #include "lpr_spook.h"
 #include "lprdem.h"
@@ -62,17 +63,6 @@ uint64_t spread3(uint64_t v) {  // 21 bits -> every third bit
   v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
   v = (v | (v << 2)) & 0x1249249249249249ULL;
   return v;
-}
-
-int host_cell_axis(const LevelGrid& G, int a, double x) {
-  double f = (x - G.lo[a]) * G.inv_w[a];
-  f = std::fmin(std::fmax(f, -1.0), (double)G.n[a]);
-  int c = (int)std::floor(f);
-  if (G.per[a]) {
-    if (c >= G.n[a]) c -= G.n[a];
-    if (c < 0) c += G.n[a];
-  }
-  return c < 0 ? 0 : (c >= G.n[a] ? G.n[a] - 1 : c);
 }
 
 bool finite_arr(const double* a, int64_t n) {
@@ -300,6 +290,7 @@ void plan_bed(const lpr_bed_desc* D, double band_ratio, double cell_factor, doub
         G.n[a] = nc;
         G.lo[a] = 0.0;
         G.inv_w[a] = (double)nc / D->box[a];
+        G.w[a] = D->box[a] / (double)nc;
         G.per[a] = 1;
       } else {
         const double lo = lo3[a] - 2.0 * hcell, hi = hi3[a] + 2.0 * hcell;
@@ -308,6 +299,7 @@ void plan_bed(const lpr_bed_desc* D, double band_ratio, double cell_factor, doub
         G.n[a] = nc;
         G.lo[a] = lo;
         G.inv_w[a] = 1.0 / hcell;
+        G.w[a] = hcell;
         G.per[a] = 0;
       }
     }
@@ -331,9 +323,9 @@ void plan_bed(const lpr_bed_desc* D, double band_ratio, double cell_factor, doub
   std::vector<uint64_t> key(n);
   for (int64_t i = 0; i < n; ++i) {
     const LevelGrid& G = levels[H.lev0 + lev_of[i]];
-    const uint64_t cx = (uint64_t)host_cell_axis(G, 0, D->pos[3 * i]);
-    const uint64_t cy = (uint64_t)host_cell_axis(G, 1, D->pos[3 * i + 1]);
-    const uint64_t cz = (uint64_t)host_cell_axis(G, 2, D->pos[3 * i + 2]);
+    const uint64_t cx = (uint64_t)cell_axis(G, 0, D->pos[3 * i]);
+    const uint64_t cy = (uint64_t)cell_axis(G, 1, D->pos[3 * i + 1]);
+    const uint64_t cz = (uint64_t)cell_axis(G, 2, D->pos[3 * i + 2]);
     key[i] = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
   }
   std::sort(H.perm.begin(), H.perm.end(), [&](int64_t a, int64_t b) {
@@ -663,7 +655,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   ok &= dal(b, &d.sid, N) && dal(b, &d.meta, N) && dal(b, &d.chunk_bed32, N / PAD);
   ok &= dal(b, &d.cell_cnt, cell_base) && dal(b, &d.cell_start, cell_base + 1);
   ok &= dal(b, &d.pcell, N) && dal(b, &d.prank, N) && dal(b, &d.cell_list, N);
-  ok &= dal(b, &d.crec, N) && dal(b, &d.cpf, N) && dal(b, &d.zext, 2 * levels.size());
+  ok &= dal(b, &d.crec, N) && dal(b, &d.cpf, N + CPF_PAD) && dal(b, &d.zext, 2 * levels.size());
   ok &= dal(b, &d.disp, N) && dal(b, &d.viol, 2);
   ok &= dal(b, &d.own_rank, (size_t)K * N) && dal(b, &d.rev_cnt, N) && dal(b, &d.rev_start, N + 1);
   ok &= dal(b, &d.rev_ent, (size_t)K * N);
@@ -822,6 +814,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   e = (hipError_t)(e | hipMemsetAsync(d.err, 0, sizeof(uint32_t), st));
   e = (hipError_t)(e | hipMemsetAsync(d.stat, 0, sizeof(uint32_t) * 4, st));
   e = (hipError_t)(e | hipMemsetAsync(d.disp, 0, sizeof(float) * N, st));
+  e = (hipError_t)(e | hipMemsetAsync(d.cpf + N, 0, sizeof(float4) * CPF_PAD, st));
   e = (hipError_t)(e | hipMemsetAsync(d.viol, 0, sizeof(uint32_t) * 2, st));
   e = (hipError_t)(e | hipMemsetAsync(d.zext, 0, sizeof(uint32_t) * 2 * levels.size(), st));
   e = (hipError_t)(e | hipMemsetAsync(d.partial, 0, sizeof(double) * d.nblk * 6 * std::max(1, body_total), st));
