@@ -918,12 +918,27 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
   const bool active = (m != INACTIVE);
   const int s = p.s, sn = p.s ^ 1, h = p.h, hn = p.h ^ 1, l = p.l;
 
+  // the block's own states in LDS: storage follows the cell order, so most
+  // partners lie in the same block and are read from here
+  __shared__ PState sst[BS];
+  const int64_t b0 = blk * BS;
+  const PState me = d.st[s][i];
+  sst[threadIdx.x] = me;
+  __syncthreads();
+  auto state_of = [&](int64_t j) -> PState {
+    PState o;
+    if ((uint64_t)(j - b0) < (uint64_t)BS)
+      o = sst[j - b0];
+    else
+      o = d.st[s][j];
+    return o;
+  };
+
   double4 xi = make_double4(0, 0, 0, 0);
   float4 vi = make_float4(0, 0, 0, 0), wi = make_float4(0, 0, 0, 0);
   float3 F = f3(0.f, 0.f, 0.f), T = f3(0.f, 0.f, 0.f);
   uint32_t fnew = 0u;
   if (active) {
-    const PState me = d.st[s][i];
     xi = me.x;
     vi = me.v;
     wi = me.w;
@@ -947,7 +962,7 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
         k_n = (int)(pk & 15u);
         oth_n = o_n;
       }
-      ot_n = d.st[s][oth_n];
+      ot_n = state_of(oth_n);
       hr_n = d.hist[h][k_n * N + o_n];
     }
     for (int e = 0; e < n_tot; ++e) {
@@ -967,7 +982,7 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
           k_n = (int)(pk & 15u);
           oth_n = o_n;
         }
-        ot_n = d.st[s][oth_n];
+        ot_n = state_of(oth_n);
         hr_n = d.hist[h][k_n * N + o_n];
       }
       const double4 xo_ = ot.x;
