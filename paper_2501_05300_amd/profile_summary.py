@@ -49,7 +49,7 @@ def kernel_source_hash() -> str:
     """Hash of the device code (comments and layout ignored); a counter
     record is valid only for it."""
     h = hashlib.sha256()
-    for f in ("lpr_dev.h", "lpr_kernels.hip"):
+    for f in ("lpr_dev.h", "lpr_cells.h", "lpr_kernels.hip"):
         with open(os.path.join(ROOT, "paper_2501_05300_amd", "csrc", f), encoding="utf-8") as fh:
             h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
