@@ -50,6 +50,7 @@ constexpr int MAXW = 16;         // walls per bed
 constexpr int MAXB = 4;          // bodies per bed
 constexpr int PAD = 256;         // per-bed particle range alignment
 constexpr int MAXLEV = 16;       // cell-list levels per bed
+constexpr int ADV_CH = 32;       // chunks of the two-level reaction reduction per bed
 constexpr int CPF_PAD = 8;       // readable entries past the end of the cell-ordered FP32 copy
 constexpr uint32_t INACTIVE = 0xffffffffu;
 constexpr int WALL_BIT = 16;

@@ -47,6 +47,8 @@ struct DevBufs {
   int32_t nwall_max;
   double* partial;       // [bodies][6][nblk] block partial sums of reactions
   int64_t nblk;          // blocks of the smallest step-kernel block size (N / 64)
+  double* adv_chunk;     // [beds][MAXB][ADV_CH][6] chunk sums of the reaction partials
+  uint32_t* adv_cnt;     // [beds] chunks summed this step (cleared by the last)
   // scan scratch
   uint32_t* scan_tmp;
   CRec* crec;            // position, radius and stable id in cell-list order (rebuild)
@@ -110,7 +112,7 @@ struct StepPar {
   bool rebuild;
 };
 
-void launch_zero(uint32_t* p, int64_t n, hipStream_t st);
+void launch_zero(uint32_t* p, int64_t n, uint32_t* q, int64_t m, hipStream_t st);
 // sort = 1 also writes each particle's sort key (level base + Morton rank
 // of its cell) and storage index.
 void launch_bin(const DevBufs& d, int s, int sort, hipStream_t st);

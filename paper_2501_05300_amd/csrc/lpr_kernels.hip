@@ -29,16 +29,22 @@ LPR_DEV_INLINE bool latched(const uint32_t* err) { return *(const volatile uint3
 // ---------------------------------------------------------------------------
 // helpers
 
-__global__ void k_zero(uint32_t* p, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0u;
+// Clears two arrays in one launch (the rebuild's cell and reverse counters).
+__global__ void k_zero(uint32_t* p, int64_t n, uint32_t* q, int64_t m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n + m; i += stride) {
+    if (i < n)
+      p[i] = 0u;
+    else
+      q[i - n] = 0u;
+  }
 }
 
-void launch_zero(uint32_t* p, int64_t n, hipStream_t st) {
-  if (n <= 0) return;
-  int64_t blocks = (n + 255) / 256;
+void launch_zero(uint32_t* p, int64_t n, uint32_t* q, int64_t m, hipStream_t st) {
+  if (n + m <= 0) return;
+  int64_t blocks = (n + m + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, p, n, q, m);
 }
 
 // Work block handled by launch block b of a grid of g blocks: the blocks
@@ -210,28 +216,14 @@ __global__ void k_scan_tiles(const uint32_t* in, uint32_t* tsum, int64_t n) {
   if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
 }
 
-__global__ void k_scan_top(uint32_t* tsum, int64_t ntiles) {
-  uint32_t carry = 0;
-  for (int64_t b0 = 0; b0 < ntiles; b0 += STILE) {
-    const int64_t base = b0 + threadIdx.x * SIPT;
-    uint32_t v[SIPT];
-    uint32_t s = 0;
-    for (int q = 0; q < SIPT; ++q) {
-      v[q] = (base + q < ntiles) ? tsum[base + q] : 0u;
-      s += v[q];
-    }
-    uint32_t tot;
-    uint32_t off = block_excl_scan(s, &tot) + carry;
-    for (int q = 0; q < SIPT; ++q) {
-      if (base + q < ntiles) tsum[base + q] = off;
-      off += v[q];
-    }
-    carry += tot;
-    __syncthreads();
-  }
-}
-
-__global__ void k_scan_apply(const uint32_t* in, uint32_t* out, const uint32_t* toff, int64_t n) {
+// Each tile's offset is the sum of the earlier tiles' sums, added up by the
+// tile's own block (a few coalesced reads per thread: the sums of a few
+// thousand tiles), then the tile is scanned.
+__global__ void k_scan_apply(const uint32_t* in, uint32_t* out, const uint32_t* tsum, int64_t n) {
+  uint32_t pre = 0;
+  for (int64_t t = threadIdx.x; t < (int64_t)blockIdx.x; t += SB) pre += tsum[t];
+  uint32_t toff;
+  block_excl_scan(pre, &toff);
   const int64_t base = blockIdx.x * (int64_t)STILE + threadIdx.x * SIPT;
   uint32_t v[SIPT];
   uint32_t s = 0;
@@ -240,7 +232,7 @@ __global__ void k_scan_apply(const uint32_t* in, uint32_t* out, const uint32_t* 
     s += v[q];
   }
   uint32_t tot;
-  uint32_t off = block_excl_scan(s, &tot) + toff[blockIdx.x];
+  uint32_t off = block_excl_scan(s, &tot) + toff;
   for (int q = 0; q < SIPT; ++q) {
     if (base + q < n) out[base + q] = off;
     if (base + q == n - 1) out[n] = off + v[q];
@@ -253,7 +245,6 @@ size_t scan_tmp_elems(int64_t n) { return (size_t)((n + STILE - 1) / STILE) + 1;
 void launch_scan(uint32_t* cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipStream_t st) {
   const int64_t tiles = (n + STILE - 1) / STILE;
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SB), 0, st, cnt, tmp, n);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SB), 0, st, tmp, tiles);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(SB), 0, st, cnt, start, tmp, n);
 }
 
@@ -1251,32 +1242,39 @@ LPR_DEV_INLINE void make_pose(const WallDef& W, const BodyDef& B, const BodyDyn&
   P.body = W.body;
 }
 
-constexpr int ADV_BS = 1024;
+// Ordered reduction of the reaction partials in two levels: ADV_CH blocks
+// per bed each sum one contiguous chunk of the block partials (a fixed
+// order: strided per thread, a shuffle tree per wave, waves ascending) and
+// store the chunk's sums; the block that finishes last (a counter per bed)
+// adds the chunk sums in chunk order, advances the bed's bodies and poses
+// and clears the counter.  Every sum has the same terms in the same order
+// whatever the timing.
+constexpr int ADV_BS = 256;
 
 __global__ __launch_bounds__(ADV_BS) void k_advance(DevBufs d, int step_block) {
   __shared__ double red[ADV_BS / 64][6];
-  __shared__ double tot_s[6];
-  if (__syncthreads_or(latched(d.err) ? 1 : 0)) return;  // uniform per block
-  const int bed = blockIdx.x;
+  __shared__ double tot_s[MAXB][6];
+  __shared__ int last_s;
+  if (__syncthreads_or(latched(d.err) ? 1 : 0)) return;  // uniform over the launch
+  const int bed = blockIdx.x / ADV_CH, ch = blockIdx.x % ADV_CH;
   const BedConst bc = d.beds[bed];
   const int64_t blk0 = bc.p0 / step_block, blk1 = bc.p1 / step_block;
+  const int64_t len = (blk1 - blk0 + ADV_CH - 1) / ADV_CH;
+  const int64_t c0 = blk0 + ch * len, c1 = (c0 + len < blk1) ? c0 + len : blk1;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int b = 0; b < bc.nbody; ++b) {
-    // fixed order: each thread sums its strided partials in ascending block
-    // order (four per component in flight), then the wave's threads by a
-    // shuffle tree, then the waves in ascending order
     double acc[6] = {0, 0, 0, 0, 0, 0};
     const double* part = d.partial + (int64_t)(bc.body0 + b) * 6 * d.nblk;
-    for (int64_t q0 = blk0 + threadIdx.x; q0 < blk1; q0 += 4 * ADV_BS) {
-      double v[4][6];
+    for (int64_t q0 = c0 + threadIdx.x; q0 < c1; q0 += 2 * ADV_BS) {
+      double v[2][6];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 2; ++u) {
         const int64_t q = q0 + (int64_t)u * ADV_BS;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) v[u][c] = (q < blk1) ? part[(int64_t)c * d.nblk + q] : 0.0;
+        for (int c = 0; c < 6; ++c) v[u][c] = (q < c1) ? part[(int64_t)c * d.nblk + q] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int c = 0; c < 6; ++c) acc[c] += v[u][c];
     }
@@ -1287,28 +1285,42 @@ __global__ __launch_bounds__(ADV_BS) void k_advance(DevBufs d, int step_block) {
     }
     __syncthreads();
     if (threadIdx.x < 6) {
-      double s = 0.0;
-      for (int q = 0; q < ADV_BS / 64; ++q) s += red[q][threadIdx.x];
-      tot_s[threadIdx.x] = s;
+      double sc = 0.0;
+      for (int q = 0; q < ADV_BS / 64; ++q) sc += red[q][threadIdx.x];
+      d.adv_chunk[(((int64_t)bed * MAXB + b) * ADV_CH + ch) * 6 + threadIdx.x] = sc;
     }
     __syncthreads();
-    double tot[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) tot[c] = tot_s[c];
-    __syncthreads();
-    if (threadIdx.x == 0) {
+  }
+  // the chunk sums are visible to every XCD before the count is raised
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last_s = (atomicAdd(&d.adv_cnt[bed], 1u) == (uint32_t)(ADV_CH - 1)) ? 1 : 0;
+  __syncthreads();
+  if (!last_s) return;
+  __threadfence();
+  if (threadIdx.x < 6 * bc.nbody) {
+    const int b = threadIdx.x / 6, c = threadIdx.x % 6;
+    const double* cs = d.adv_chunk + ((int64_t)bed * MAXB + b) * ADV_CH * 6;
+    double sc = 0.0;
+    for (int q = 0; q < ADV_CH; ++q) sc += __hip_atomic_load(&cs[q * 6 + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    tot_s[b][c] = sc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int b = 0; b < bc.nbody; ++b) {
       BodyDyn& D = d.bdyn[bc.body0 + b];
       const BodyDef& B = d.bdefs[bc.body0 + b];
       for (int c = 0; c < 6; ++c) {
-        D.last[c] = tot[c];
-        D.wsum[c] += tot[c];
+        D.last[c] = tot_s[b][c];
+        D.wsum[c] += tot_s[b][c];
       }
       D.wsteps += 1;
       if (B.z_free) {
-        D.vz = D.vz + bc.dt_d * (tot[2] / B.mass + (double)bc.g[2]);
+        D.vz = D.vz + bc.dt_d * (tot_s[b][2] / B.mass + (double)bc.g[2]);
         D.z = D.z + bc.dt_d * D.vz;
       }
     }
+    d.adv_cnt[bed] = 0u;
   }
   __syncthreads();
   // poses for the next step
@@ -1326,7 +1338,7 @@ __global__ __launch_bounds__(ADV_BS) void k_advance(DevBufs d, int step_block) {
 }
 
 void launch_advance(const DevBufs& d, int step_block, hipStream_t st) {
-  hipLaunchKernelGGL(k_advance, dim3((unsigned)d.nbeds), dim3(ADV_BS), 0, st, d, step_block);
+  hipLaunchKernelGGL(k_advance, dim3((unsigned)(d.nbeds * ADV_CH)), dim3(ADV_BS), 0, st, d, step_block);
 }
 
 __global__ void k_poses(DevBufs d) {

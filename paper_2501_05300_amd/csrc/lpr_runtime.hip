@@ -444,8 +444,7 @@ void mark(lpr_bed* b, int k) {
 void enqueue_rebuild(lpr_bed* b) {
   DevBufs& d = b->d;
   const bool srt = b->sort_every > 0 && !b->sort_hold && b->sc == 0;
-  launch_zero(d.cell_cnt, d.ncells, b->stream);
-  launch_zero(d.rev_cnt, d.N, b->stream);
+  launch_zero(d.cell_cnt, d.ncells, d.rev_cnt, d.N, b->stream);
   launch_bin(d, b->s, srt ? 1 : 0, b->stream);
   launch_scan(d.cell_cnt, d.cell_start, d.scan_tmp, d.ncells, b->stream);
   mark(b, 1);
@@ -676,6 +675,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   for (const HostBed& H : b->hb) d.n_active += H.n;
   d.nblk = N / 64;
   ok &= dal(b, &d.partial, (size_t)d.nblk * 6 * std::max(1, body_total));
+  ok &= dal(b, &d.adv_chunk, (size_t)nb * MAXB * ADV_CH * 6) && dal(b, &d.adv_cnt, (size_t)nb);
   ok &= dal(b, &d.scan_tmp, std::max(scan_tmp_elems(cell_base), scan_tmp_elems(N + 1)));
   ok &= dal(b, &d.beds, nb) && dal(b, &d.levels, levels.size());
   ok &= dal(b, &d.wdefs, std::max(1, wall_total)) && dal(b, &d.walls, std::max(1, wall_total));
@@ -818,6 +818,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   e = (hipError_t)(e | hipMemsetAsync(d.viol, 0, sizeof(uint32_t) * 2, st));
   e = (hipError_t)(e | hipMemsetAsync(d.zext, 0, sizeof(uint32_t) * 2 * levels.size(), st));
   e = (hipError_t)(e | hipMemsetAsync(d.partial, 0, sizeof(double) * d.nblk * 6 * std::max(1, body_total), st));
+  e = (hipError_t)(e | hipMemsetAsync(d.adv_cnt, 0, sizeof(uint32_t) * nb, st));
   if (b->record) {
     e = (hipError_t)(e | hipMemsetAsync(d.frc, 0, sizeof(float4) * N, st));
     e = (hipError_t)(e | hipMemsetAsync(d.trq, 0, sizeof(float4) * N, st));
