@@ -644,7 +644,7 @@ def main():
     per_step = {k: v / args.steps for k, v in prof.items()}
     phases = {k: v for k, v in per_step.items() if k != "total"}
     dom = max(phases, key=phases.get)
-    block = args.block or 256
+    block = args.block or 64
     kname = PHASE_KERNEL[dom].format(block=block)
     rec = counter_record(N)
     mode = "every_step" if args.rebuild_every == 1 else "skin_lists"

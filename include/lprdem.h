@@ -135,7 +135,7 @@ typedef struct {
   float band_ratio;        /* radius ratio of one cell-list level (0: 2) */
   float cell_factor;       /* cell edge / (2 r_max(level) + skin), >= 1 (0: 1) */
   int32_t block;           /* threads per block of the step kernel: 64, 128
-                              or 256 (0: 256) */
+                              or 256 (0: 64) */
   int32_t record_forces;   /* 1: keep the last step's per-particle contact
                               forces and torques for lpr_read_forces and its
                               per-contact loads for lpr_read_contact_loads

@@ -95,7 +95,7 @@ struct lpr_bed {
   std::vector<void*> blocks;
   DevBufs d{};
   std::vector<HostBed> hb;
-  int block = 256;
+  int block = 64;
   int persist_blocks = 0;  // > 0: persistent step kernel with this grid
   int record = 0;
   int R = 1;      // configured rebuild cadence
@@ -583,7 +583,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
     b->own_stream = true;
   }
   (void)hipGetDevice(&b->device);
-  b->block = D0.block ? D0.block : 256;
+  b->block = D0.block ? D0.block : 64;
   if (D0.persistent) {
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
@@ -1508,7 +1508,7 @@ lpr_status lpr_autotune(const lpr_bed_desc* const* descs, int32_t n_beds, const 
       for (auto& w : work) {
         w.band_ratio = br;
         w.cell_factor = cf;
-        w.block = 256;
+        w.block = 64;
         w.persistent = 0;
         w.record_forces = 0;
       }

@@ -61,7 +61,7 @@ def test_batch_bed_parity_with_oracle():
         assert_parity(res, 1e-5)
 
 
-@pytest.mark.parametrize("block,persistent", [(64, False), (128, True), (256, True), (64, True)])
+@pytest.mark.parametrize("block,persistent", [(256, False), (128, True), (256, True), (64, True)])
 def test_launch_shapes_give_identical_results(block, persistent):
     from paper_2501_05300_amd.lprdem import Batch
     specs = small_family()
