@@ -6,8 +6,10 @@
 //   scan        exclusive scan of cell counts -> cell ranges
 //   k_scatter   cell lists
 //   k_search    owner-side candidates: same level with larger (r, id), and
-//               every coarser level, 27 cells each; sorted by partner id;
-//               history carried over from the previous lists; reverse counts
+//               every coarser level within reach, in the neighbour cells
+//               whose box lies within reach; sorted by partner id; lists and
+//               springs updated in place (or moved after a re-sort);
+//               reverse counts
 //   scan        reverse ranges;  k_rev_scatter / k_rev_sort: partner-side
 //               entries in ascending owner stable id
 // then every step:
