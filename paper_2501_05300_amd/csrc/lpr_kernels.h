@@ -32,6 +32,7 @@ struct DevBufs {
   uint32_t* rev_cnt;     // [N]
   uint32_t* rev_start;   // [N+1]
   uint32_t* rev_ent;     // [K*N]
+  uint64_t* rev_tmp;     // [K*N] entries with their sort key, between the reverse scatter and sort
   // history
   HRec* hist[2];         // [K][N]
   float4* wA[2];         // [MAXW][N]

@@ -804,6 +804,9 @@ __global__ void k_rev_scatter(DevBufs d, int l) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= d.N || latched(d.err)) return;
   const int cnt = d.own_cnt[l][i];
+  // each entry is written with its sort key (the owner's stable id) in the
+  // high word, one 8-byte write, so that the sort that follows reads no ids
+  const uint64_t key = (uint64_t)(uint32_t)d.sid[i] << 32;
   // slots four at a time, their reads in flight together
   for (int k0 = 0; k0 < cnt; k0 += 4) {
     int32_t j[4];
@@ -818,7 +821,7 @@ __global__ void k_rev_scatter(DevBufs d, int l) {
     for (int u = 0; u < 4; ++u) at[u] = (k0 + u < cnt) ? d.rev_start[j[u]] + rk[u] : 0u;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (k0 + u < cnt) d.rev_ent[at[u]] = ((uint32_t)i << 4) | (uint32_t)(k0 + u);
+      if (k0 + u < cnt) d.rev_tmp[at[u]] = key | (((uint32_t)i << 4) | (uint32_t)(k0 + u));
   }
 }
 
@@ -829,50 +832,46 @@ void launch_rev_scatter(const DevBufs& d, int l, hipStream_t st) {
 // Partner-side entries of a particle in ascending stable id of the owner, so
 // that the order in which its forces are summed does not depend on the
 // storage order (and so on the cell layout); an owner holds a given partner
-// in one slot at most, so the keys are distinct.
+// in one slot at most, so the keys are distinct.  The scatter left each
+// entry beside its key (key << 32 | entry); the sorted entries are written
+// to the list the step reads.
 __global__ void k_rev_sort(DevBufs d) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= d.N || latched(d.err)) return;
   const uint32_t a = d.rev_start[j], b = d.rev_start[j + 1];
   if (b - a <= 8u) {
-    // short lists (nearly all): entries and owner ids read together, sorted
-    // in registers by an odd-even transposition network, written once
-    constexpr int32_t KMAX = 0x7fffffff;
-    uint32_t e[8];
-    int32_t key[8];
+    // short lists (nearly all): sorted in registers by an odd-even
+    // transposition network (the key decides, being in the high word)
+    uint64_t e[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) e[u] = (a + u < b) ? d.rev_ent[a + u] : 0u;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) key[u] = (a + u < b) ? d.sid[e[u] >> 4] : KMAX;
+    for (int u = 0; u < 8; ++u) e[u] = (a + u < b) ? d.rev_tmp[a + u] : ~0ull;
 #pragma unroll
     for (int r = 0; r < 8; ++r)
 #pragma unroll
       for (int u = r & 1; u + 1 < 8; u += 2)
-        if (key[u + 1] < key[u]) {
-          const int32_t tk = key[u];
-          key[u] = key[u + 1];
-          key[u + 1] = tk;
-          const uint32_t te = e[u];
+        if (e[u + 1] < e[u]) {
+          const uint64_t te = e[u];
           e[u] = e[u + 1];
           e[u + 1] = te;
         }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (a + u < b) d.rev_ent[a + u] = e[u];
+      if (a + u < b) d.rev_ent[a + u] = (uint32_t)e[u];
     return;
   }
+  // long lists: insertion sort in place over the keyed entries, then copied
   for (uint32_t q = a + 1; q < b; ++q) {
-    const uint32_t e = d.rev_ent[q];
-    const int32_t key = d.sid[e >> 4];
+    const uint64_t e = d.rev_tmp[q];
     uint32_t p = q;
     while (p > a) {
-      const uint32_t prev = d.rev_ent[p - 1];
-      if (d.sid[prev >> 4] <= key) break;
-      d.rev_ent[p] = prev;
+      const uint64_t prev = d.rev_tmp[p - 1];
+      if (prev <= e) break;
+      d.rev_tmp[p] = prev;
       --p;
     }
-    d.rev_ent[p] = e;
+    d.rev_tmp[p] = e;
   }
+  for (uint32_t q = a; q < b; ++q) d.rev_ent[q] = (uint32_t)d.rev_tmp[q];
 }
 
 void launch_rev_sort(const DevBufs& d, hipStream_t st) {

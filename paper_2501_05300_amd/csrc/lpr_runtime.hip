@@ -657,7 +657,7 @@ lpr_status create_impl(const lpr_bed_desc* const* descs, int nb, const lpr_alloc
   ok &= dal(b, &d.crec, N) && dal(b, &d.cpf, N + CPF_PAD) && dal(b, &d.zext, 2 * levels.size());
   ok &= dal(b, &d.disp, N) && dal(b, &d.viol, 2);
   ok &= dal(b, &d.own_rank, (size_t)K * N) && dal(b, &d.rev_cnt, N) && dal(b, &d.rev_start, N + 1);
-  ok &= dal(b, &d.rev_ent, (size_t)K * N);
+  ok &= dal(b, &d.rev_ent, (size_t)K * N) && dal(b, &d.rev_tmp, (size_t)K * N);
   if (b->record) {
     ok &= dal(b, &d.frc, N) && dal(b, &d.trq, N);
     ok &= dal(b, &d.cF, (size_t)K * N) && dal(b, &d.cM, (size_t)K * N);
