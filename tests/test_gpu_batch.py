@@ -99,3 +99,37 @@ def test_autotuner_returns_a_working_setting():
         xc, vc, _ = banded.state(bed=q)
         assert np.array_equal(xa, xb) and np.array_equal(va, vb), q
         assert np.array_equal(xa, xc) and np.array_equal(va, vc), q
+
+
+def test_full_batch_family_beds_match_the_oracle():
+    """The 36-bed family of the batched benchmark (2.24M spheres, each bed
+    under its own plate), stepped 40,000 times from placement as one batch
+    with skin lists (bitwise the every-step search), so that thousands of
+    contacts have formed in each bed (it is still settling): then one step of the smallest bed and of the bed
+    nearest 100k spheres against the oracle, from the same state and springs,
+    at the per-contact and per-particle bounds."""
+    from paper_2501_05300_amd.lprdem import Batch
+    specs = beds.batch_family()
+    rmin = min(float(s.radius.min()) for s in specs)
+    batch = Batch(specs, rebuild_every=10, skin=0.25 * rmin, record_forces=True)
+    batch.step(40_000)
+    batch.sync()
+    sizes = [s.n for s in specs]
+    picks = sorted({int(np.argmin(sizes)), int(np.argmin([abs(n - 100_000) for n in sizes]))})
+
+    class View:  # one bed of the batch seen through the single-bed helper
+        def __init__(self, b, q):
+            self.b, self.q = b, q
+
+        def __getattr__(self, name):
+            f = getattr(self.b, name)
+            return lambda *a, **k: f(*a, bed=self.q, **k)
+
+        def step(self, n):
+            self.b.step(n)
+
+    for q in picks:
+        res = compare_one_step(specs[q], View(batch, q))
+        print(q, specs[q].n, {k: v for k, v in res.items() if k not in ("only_gpu", "only_oracle")})
+        assert res["n_contacts"] >= 2000
+        assert_parity(res, 1e-5)
