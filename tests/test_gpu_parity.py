@@ -125,9 +125,14 @@ def test_short_trajectory_bound():
     assert err < 1e-3 * float(spec.radius.min())
 
 
-@pytest.mark.parametrize("opts", [dict(cell_factor=1.5), dict(band_ratio=1.5), dict(block=64), dict(block=128),
-                                  dict(band_ratio=8.0, cell_factor=1.25)])
+@pytest.mark.parametrize("opts", [dict(cell_factor=1.5), dict(band_ratio=1.5), dict(block=256), dict(block=128),
+                                  dict(band_ratio=8.0, cell_factor=1.25), dict(cell_factor=3.5)])
 def test_contact_list_invariant_to_broad_phase_choices(opts):
+    """Cell sizes, radius bands and launch shapes change which cells and rows
+    the search walks (cell factor 3.5 leaves the coarsest level two cells
+    across the periodic box, where every cell is taken once, and cells far
+    wider than the reach, where most rows and end cells are dropped), never
+    the contact list or the forces."""
     spec = cloud(9, n=2500)
     ref = gpu_bed(spec)
     ref.step(1)
