@@ -145,9 +145,19 @@ LPR_HD void row_set(const LevelGrid& G, const double4& pi, double reach, RowSet&
 }
 
 // Cell-list bounds [q0, q1) of the nine rows of x piece p (empty rows
-// [0, 0)).
+// [0, 0)).  Every cell id is below 2^31 (checked when the grids are laid
+// out), so row offsets are 32-bit.
 LPR_HD void row_piece(const uint32_t* __restrict__ cell_start, const LevelGrid& G, const RowSet& R, int p,
                       uint32_t q0[9], uint32_t q1[9]) {
+  const uint32_t n0 = (uint32_t)G.n[0], plane = n0 * (uint32_t)G.n[1];
+  const uint32_t zb = (uint32_t)G.base + (uint32_t)R.z0 * plane;
+  uint32_t yb[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    int y = R.y0 + b;
+    if (G.per[1]) y = (y < 0) ? y + G.n[1] : (y >= G.n[1] ? y - G.n[1] : y);
+    yb[b] = (uint32_t)y * n0;
+  }
 #pragma unroll
   for (int r = 0; r < 9; ++r) {
     const int a = r / 3, b = r % 3;
@@ -164,11 +174,9 @@ LPR_HD void row_piece(const uint32_t* __restrict__ cell_start, const LevelGrid& 
       xb = xa;
     }
     if (a < R.nzl && b < R.nyl && p < R.nxp && ((R.keep >> (3 * r)) & 1u) && xa < xb) {
-      int y = R.y0 + b;
-      if (G.per[1]) y = (y < 0) ? y + G.n[1] : (y >= G.n[1] ? y - G.n[1] : y);
-      const int64_t rb = G.base + ((int64_t)(R.z0 + a) * G.n[1] + y) * G.n[0];
-      q0[r] = cell_start[rb + xa];
-      q1[r] = cell_start[rb + xb];
+      const uint32_t rb = zb + (uint32_t)a * plane + yb[b];
+      q0[r] = cell_start[rb + (uint32_t)xa];
+      q1[r] = cell_start[rb + (uint32_t)xb];
     }
   }
 }
