@@ -31,22 +31,35 @@ LPR_DEV_INLINE bool latched(const uint32_t* err) { return *(const volatile uint3
 // ---------------------------------------------------------------------------
 // helpers
 
-// Clears two arrays in one launch (the rebuild's cell and reverse counters).
-__global__ void k_zero(uint32_t* p, int64_t n, uint32_t* q, int64_t m) {
+// Clears two arrays in one launch (the rebuild's cell and reverse counters):
+// 16-byte stores over each array's whole groups of four words when both are
+// 16-byte aligned (vec), single words otherwise and for the last few.
+__global__ void k_zero(uint32_t* p, int64_t n, uint32_t* q, int64_t m, int vec) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n + m; i += stride) {
-    if (i < n)
-      p[i] = 0u;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t n4 = vec ? n / 4 : 0, m4 = vec ? m / 4 : 0;
+  for (int64_t i = t0; i < n4 + m4; i += stride) {
+    if (i < n4)
+      reinterpret_cast<uint4*>(p)[i] = make_uint4(0u, 0u, 0u, 0u);
     else
-      q[i - n] = 0u;
+      reinterpret_cast<uint4*>(q)[i - n4] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  const int64_t rn = n - 4 * n4, rm = m - 4 * m4;
+  for (int64_t i = t0; i < rn + rm; i += stride) {
+    if (i < rn)
+      p[4 * n4 + i] = 0u;
+    else
+      q[4 * m4 + (i - rn)] = 0u;
   }
 }
 
 void launch_zero(uint32_t* p, int64_t n, uint32_t* q, int64_t m, hipStream_t st) {
   if (n + m <= 0) return;
-  int64_t blocks = (n + m + 255) / 256;
+  const int vec = ((reinterpret_cast<uintptr_t>(p) | reinterpret_cast<uintptr_t>(q)) & 15u) == 0u ? 1 : 0;
+  const int64_t work = vec ? (n + m) / 4 + 8 : n + m;
+  int64_t blocks = (work + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, p, n, q, m);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, p, n, q, m, vec);
 }
 
 // Work block handled by launch block b of a grid of g blocks: the blocks
@@ -208,11 +221,24 @@ LPR_DEV_INLINE uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
   return off + x - v;
 }
 
-__global__ void k_scan_tiles(const uint32_t* in, uint32_t* tsum, int64_t n) {
+// A thread's eight counts: two 16-byte reads where all eight lie inside and
+// the array is 16-byte aligned (base is a multiple of eight).
+LPR_DEV_INLINE void load8(const uint32_t* in, int64_t base, int64_t n, bool vec, uint32_t v[SIPT]) {
+  if (vec && base + SIPT <= n) {
+    const uint4 a = *reinterpret_cast<const uint4*>(in + base), b = *reinterpret_cast<const uint4*>(in + base + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+    for (int q = 0; q < SIPT; ++q) v[q] = (base + q < n) ? in[base + q] : 0u;
+  }
+}
+
+__global__ void k_scan_tiles(const uint32_t* in, uint32_t* tsum, int64_t n, int vec) {
   const int64_t base = blockIdx.x * (int64_t)STILE + threadIdx.x * SIPT;
+  uint32_t v[SIPT];
+  load8(in, base, n, vec != 0, v);
   uint32_t s = 0;
-  for (int q = 0; q < SIPT; ++q)
-    if (base + q < n) s += in[base + q];
+  for (int q = 0; q < SIPT; ++q) s += v[q];
   uint32_t tot;
   block_excl_scan(s, &tot);
   if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
@@ -221,24 +247,32 @@ __global__ void k_scan_tiles(const uint32_t* in, uint32_t* tsum, int64_t n) {
 // Each tile's offset is the sum of the earlier tiles' sums, added up by the
 // tile's own block (a few coalesced reads per thread: the sums of a few
 // thousand tiles), then the tile is scanned.
-__global__ void k_scan_apply(const uint32_t* in, uint32_t* out, const uint32_t* tsum, int64_t n) {
+__global__ void k_scan_apply(const uint32_t* in, uint32_t* out, const uint32_t* tsum, int64_t n, int vec) {
   uint32_t pre = 0;
   for (int64_t t = threadIdx.x; t < (int64_t)blockIdx.x; t += SB) pre += tsum[t];
   uint32_t toff;
   block_excl_scan(pre, &toff);
   const int64_t base = blockIdx.x * (int64_t)STILE + threadIdx.x * SIPT;
   uint32_t v[SIPT];
+  load8(in, base, n, vec != 0, v);
   uint32_t s = 0;
-  for (int q = 0; q < SIPT; ++q) {
-    v[q] = (base + q < n) ? in[base + q] : 0u;
-    s += v[q];
-  }
+  for (int q = 0; q < SIPT; ++q) s += v[q];
   uint32_t tot;
   uint32_t off = block_excl_scan(s, &tot) + toff;
+  uint32_t o[SIPT];
   for (int q = 0; q < SIPT; ++q) {
-    if (base + q < n) out[base + q] = off;
-    if (base + q == n - 1) out[n] = off + v[q];
+    o[q] = off;
     off += v[q];
+  }
+  if (vec && base + SIPT <= n) {
+    *reinterpret_cast<uint4*>(out + base) = make_uint4(o[0], o[1], o[2], o[3]);
+    *reinterpret_cast<uint4*>(out + base + 4) = make_uint4(o[4], o[5], o[6], o[7]);
+    if (base + SIPT == n) out[n] = off;
+  } else {
+    for (int q = 0; q < SIPT; ++q) {
+      if (base + q < n) out[base + q] = o[q];
+      if (base + q == n - 1) out[n] = o[q] + v[q];
+    }
   }
 }
 
@@ -246,8 +280,9 @@ size_t scan_tmp_elems(int64_t n) { return (size_t)((n + STILE - 1) / STILE) + 1;
 
 void launch_scan(uint32_t* cnt, uint32_t* start, uint32_t* tmp, int64_t n, hipStream_t st) {
   const int64_t tiles = (n + STILE - 1) / STILE;
-  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SB), 0, st, cnt, tmp, n);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(SB), 0, st, cnt, start, tmp, n);
+  const int vec = ((reinterpret_cast<uintptr_t>(cnt) | reinterpret_cast<uintptr_t>(start)) & 15u) == 0u ? 1 : 0;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SB), 0, st, cnt, tmp, n, vec);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(SB), 0, st, cnt, start, tmp, n, vec);
 }
 
 // ---------------------------------------------------------------------------
