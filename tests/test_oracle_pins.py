@@ -230,6 +230,52 @@ def test_rolling_resistance_deceleration():
     assert abs(a - (-(5.0 / 7.0) * mu_r * 9.81)) < 0.01 * (5.0 / 7.0) * mu_r * 9.81
 
 
+def test_stuck_contact_vibrates_with_the_spring_stiffnesses():
+    """A sphere resting on the floor is nudged sideways, with friction high
+    enough that its springs never slip and no damping.  The tangential spring
+    k_t = kappa_t dF_n/d(delta) (kappa_t the Mindlin ratio 2(1 - nu)/(2 - nu)
+    of the material's nu) at the contact point, a lever r - delta/2 below the
+    centre, and the rolling spring k_r = k_t r*^2 (r* = r on a wall) make a
+    two-degree-of-freedom oscillator of the centre and the rotation.  Its
+    step-by-step solution (springs advanced by the contact-point and relative
+    angular velocities, then velocities, then positions) is iterated here on
+    its own; a wrong stiffness, lever, torque sign or inertia changes its
+    frequencies, so the oracle would drift away from it within a period."""
+    prm = beds.Params(rho=2600.0, mu_t=10.0, mu_r=10.0, gamma_factor=0.0, dt=2e-6)
+    r = float(np.float32(1.5e-3))
+    m = prm.rho * 4.0 / 3.0 * math.pi * r ** 3
+    inertia = 0.4 * m * r * r
+    Estar = prm.E / (2 * (1 - prm.nu ** 2))
+    kn = Estar * math.sqrt(2 * r) / 3.0
+    dstat = (m * 9.81 / kn) ** (2.0 / 3.0)
+    spec = make_spec([[0.01, 0.01, r - dstat]], [r], vel=[[1e-4, 0, 0]], params=prm,
+                     walls=[beds.floor_wall()], box=(1, 1, 0))
+    b = O.OracleBed(spec)
+    p0, v0, w0 = b.state()
+    delta = r - p0[0, 2]
+    kt = prm.kappa() * 1.5 * kn * math.sqrt(delta)  # e_H = 5/4: F_n = k_n delta^(3/2)
+    kr = kt * r * r
+    la = r - 0.5 * delta
+    dt = prm.dt
+    v, w, xt, xr = float(v0[0, 0]), float(w0[0, 1]), 0.0, 0.0
+    vmax, wmax, vmin = 0.0, 0.0, 0.0
+    for _ in range(2000):
+        b.step(1)
+        xt += dt * (v - la * w)      # contact point slides with v - la w
+        xr += dt * w
+        F = -kt * xt
+        tq = -la * F - kr * xr       # lever below the centre, rolling moment
+        v += dt * F / m
+        w += dt * tq / inertia
+        _, vo, wo = b.state()
+        vmax = max(vmax, abs(vo[0, 0] - v))
+        wmax = max(wmax, abs(wo[0, 1] - w))
+        vmin = min(vmin, v)
+    assert vmin < -0.5e-4               # the motion reverses: a real oscillation
+    assert vmax < 1e-6 * 1e-4
+    assert wmax < 1e-6 * 1e-4 / r
+
+
 # ---------------------------------------------------------------------------
 # P-6: momentum balance with walls removed
 
