@@ -175,6 +175,49 @@ def test_explicit_step_on_an_incline_on_the_gpu(mu, rolls):
     assert abs(a / ref - 1.0) < 1e-3, (a, ref)
 
 
+def test_stuck_contact_vibrates_with_the_spring_stiffnesses_on_the_gpu():
+    """A sphere resting on the floor, nudged sideways with friction too high
+    to slip and no damping, through the HIP step: it follows the
+    two-degree-of-freedom oscillator that the tangential spring
+    k_t = kappa_t dF_n/d(delta) at the lever r - delta/2 and the rolling
+    spring k_r = k_t r^2 make, iterated here on its own (FP32 law and
+    velocities: to 2e-3 of the initial speed over 13 periods)."""
+    from paper_2501_05300_amd.lprdem import Bed
+    prm = beds.Params(rho=2600.0, mu_t=10.0, mu_r=10.0, gamma_factor=0.0, dt=2e-6)
+    r = float(np.float32(1.5e-3))
+    m = prm.rho * 4.0 / 3.0 * math.pi * r ** 3
+    inertia = 0.4 * m * r * r
+    kn = prm.E / (2 * (1 - prm.nu ** 2)) * math.sqrt(2 * r) / 3.0
+    dstat = (m * 9.81 / kn) ** (2.0 / 3.0)
+    spec = spec_of([[0.01, 0.01, r - dstat]], [r], box=(1.0, 1.0, 0.0), periodic=0, params=prm,
+                   walls=[beds.floor_wall()])
+    spec.vel[0, 0] = 1e-4
+    bed = Bed(spec)
+    p0, v0, w0 = bed.state()
+    delta = r - float(p0[0, 2])
+    kt = prm.kappa() * 1.5 * kn * math.sqrt(delta)
+    kr = kt * r * r
+    la = r - 0.5 * delta
+    dt = prm.dt
+    v, w, xt, xr = float(v0[0, 0]), float(w0[0, 1]), 0.0, 0.0
+    dv, dw, vmin = 0.0, 0.0, 0.0
+    for _ in range(2000):
+        bed.step(1)
+        xt += dt * (v - la * w)
+        xr += dt * w
+        F = -kt * xt
+        tq = -la * F - kr * xr
+        v += dt * F / m
+        w += dt * tq / inertia
+        _, vg, wg = bed.state()
+        dv = max(dv, abs(float(vg[0, 0]) - v))
+        dw = max(dw, abs(float(wg[0, 1]) - w))
+        vmin = min(vmin, v)
+    assert vmin < -0.5e-4
+    assert dv < 2e-3 * 1e-4, dv
+    assert dw < 2e-3 * 1e-4 / r, dw
+
+
 def test_sphere_through_the_floor_latches():
     """A sphere whose centre is set below the floor by more than its radius
     has tunnelled: the step latches LPR_E_DOMAIN, reported at lpr_sync; the
