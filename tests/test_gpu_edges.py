@@ -1,6 +1,7 @@
 """Edge cases of the HIP stepper: a lone sphere, rejected descriptions, a
 particle with more partners than slots and one with exactly as many, cells
-too crowded for the search's row table, coincident spheres (GPU)."""
+too crowded for the search's row table, coincident spheres, and closed-form
+motion on an incline and of a stuck contact (GPU)."""
 import math
 
 import numpy as np
