@@ -978,13 +978,41 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
     int k_n = 0;
     PState ot_n{};
     HRec hr_n{};
+    // the first PRE slot partners and partner-side entries are read together
+    // before the loop (most particles have no more), so that a contact's
+    // partner state is requested without first waiting for its index
+    constexpr int PRE = 8;
+    const int n_rev = n_tot - n_own;
+    int32_t pre_o[PRE];
+    uint32_t pre_r[PRE];
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) {
+      pre_o[u] = (u < n_own) ? d.own_idx[l][(int64_t)u * N + i] : 0;
+      pre_r[u] = (u < n_rev) ? d.rev_ent[rs + u] : 0u;
+    }
+    auto own_at = [&](int k2) -> int64_t {
+      int32_t v = 0;
+      bool hit = false;
+#pragma unroll
+      for (int u = 0; u < PRE; ++u)
+        if (k2 == u) { v = pre_o[u]; hit = true; }
+      return hit ? (int64_t)v : (int64_t)d.own_idx[l][(int64_t)k2 * N + i];
+    };
+    auto rev_at = [&](int q) -> uint32_t {
+      uint32_t v = 0u;
+      bool hit = false;
+#pragma unroll
+      for (int u = 0; u < PRE; ++u)
+        if (q == u) { v = pre_r[u]; hit = true; }
+      return hit ? v : d.rev_ent[rs + q];
+    };
     if (n_tot > 0) {
       if (n_own > 0) {
         k_n = 0;
         o_n = i;
-        oth_n = d.own_idx[l][i];
+        oth_n = own_at(0);
       } else {
-        const uint32_t pk = d.rev_ent[rs];
+        const uint32_t pk = rev_at(0);
         o_n = pk >> 4;
         k_n = (int)(pk & 15u);
         oth_n = o_n;
@@ -992,6 +1020,9 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
       ot_n = state_of(oth_n);
       hr_n = d.hist[h][k_n * N + o_n];
     }
+    // not unrolled or peeled: one copy of the law evaluates both sides of
+    // every pair, so their forces are exactly opposite
+#pragma clang loop unroll(disable)
     for (int e = 0; e < n_tot; ++e) {
       const int64_t o = o_n;
       const int k = k_n;
@@ -1002,9 +1033,9 @@ __device__ __forceinline__ void step_block(const DevBufs& d, const StepPar& p, i
         if (e + 1 < n_own) {
           k_n = e + 1;
           o_n = i;
-          oth_n = d.own_idx[l][(int64_t)k_n * N + i];
+          oth_n = own_at(k_n);
         } else {
-          const uint32_t pk = d.rev_ent[rs + (e + 1 - n_own)];
+          const uint32_t pk = rev_at(e + 1 - n_own);
           o_n = pk >> 4;
           k_n = (int)(pk & 15u);
           oth_n = o_n;
